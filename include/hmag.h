@@ -1,0 +1,152 @@
+/*
+ * hmag.h -- C-ABI of libhmag: numerically exact magic of pure state vectors on AMD MI355X (gfx950).
+ *
+ * Computes, for a state vector psi of N qudits:
+ *   - qubits (d = 2): the stabilizer Renyi entropies M_q (Eq. sre of "Computing quantum magic of
+ *     state vectors", Sec. 2) by Algorithm 2: for every X-string a, the vector
+ *     v_x = conj(psi_{x XOR a}) psi_x is Walsh-Hadamard transformed (Eqs. Z_FT_qubits, Z_ovN) to give
+ *     chi_b(a) = <psi|X_a Z_b|psi> for all Z-strings b, and S_q = sum_{a,b} |chi_b(a)|^{2q};
+ *   - qutrits (d = 3): the pure-state mana (Eq. mana2) by Algorithm 4: for every shift a in Z_3^N,
+ *     v_x = conj(alpha_x) alpha_{-x} with alpha = X_a psi is transformed by F_3^{(x)N},
+ *     (F_3)_{jk} = omega^{2jk} (Eqs. mana_FT, F3_unnorm_def), and m = sum_{a,b} |chi_b(a)|.
+ *
+ * Conventions shared by every entry point
+ *   - State layout: psi[x] for basis index x = sum_k x_k d^k (qudit k is digit k, little-endian),
+ *     interleaved (re, im): HM_C64 = 2 x float per amplitude, HM_C128 = 2 x double.
+ *   - Pointers named psi, out, sums, rows, row_sums, grad, ws are DEVICE pointers (HIP global
+ *     memory of the current device), owned by the caller; the library never frees or retains them.
+ *     psi must be 8-byte (C64) or 16-byte (C128) aligned; ws must be 256-byte aligned.
+ *   - q (Renyi indices) is a HOST array of n_q doubles, 1 <= n_q <= HM_MAX_Q, each q > 0 and finite.
+ *     q == 1 means the Shannon limit M_1 = -2^{-N} sum_P <P>^2 log2 <P>^2.
+ *   - Work is enqueued on `stream` (NULL = the default stream) and is stream-ordered: buffers must
+ *     stay alive until the stream has consumed them.  Results are written to device memory; no call
+ *     synchronises the host unless its description says so.
+ *   - Every argument is validated on the host before anything is enqueued; on error nothing is
+ *     launched and the outputs are untouched.  The detailed message of the last error on the calling
+ *     thread is available from hm_last_error().
+ *   - The state is not renormalised (S_q scales as |psi|^{4q}); lost_norm reports 1 - sum_P <P>^2/2^N.
+ *   - Results are bitwise reproducible for a fixed (entry point, n, dtype, q list, library build).
+ *   - Floating point: HM_C128 runs the transforms and sums in FP64.  HM_C64 runs the transforms in
+ *     FP32 and accumulates every sum over Pauli strings / phase-space points in FP64 (each thread
+ *     sums at most 64 FP32 terms before widening).
+ */
+#ifndef HMAG_H
+#define HMAG_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HM_MAX_Q 8
+
+typedef enum {
+  HM_OK = 0,
+  HM_E_ARG = 1,         /* null/invalid pointer or argument (message says which)              */
+  HM_E_DTYPE = 2,       /* dtype not HM_C64 / HM_C128                                          */
+  HM_E_SIZE = 3,        /* n outside the supported range for this entry point                  */
+  HM_E_WORKSPACE = 4,   /* ws_bytes smaller than the size the matching *_workspace call gives   */
+  HM_E_UNSUPPORTED = 5, /* valid request this build does not implement (message says what)    */
+  HM_E_HIP = 6,         /* a HIP runtime call failed (message carries hipGetErrorString)       */
+  HM_E_ALIGN = 7        /* a pointer violates the alignment stated above                      */
+} hm_status;
+
+typedef enum { HM_C64 = 0, HM_C128 = 1 } hm_dtype;
+
+/* Library context: holds per-device launch plans and options; owns no device memory. */
+typedef struct hm_context *hm_handle;
+
+hm_status hm_create(hm_handle *h);
+hm_status hm_destroy(hm_handle h);
+const char *hm_status_string(hm_status s);
+/* Message describing the most recent failure on the calling thread ("" if none). */
+const char *hm_last_error(void);
+/* Version string of this build. */
+const char *hm_version(void);
+
+/* Options (testing and tuning).  HM_OPT_FORCE_PATH selects the SRE kernel family:
+ *   0 = automatic, 1 = workgroup-resident (one workgroup holds a whole folded shift vector),
+ *   2 = two-pass (row pass, exchange through device memory, column pass).
+ * A forced path outside its supported n range makes the SRE calls return HM_E_UNSUPPORTED.
+ * HM_OPT_BATCH_SHIFTS sets how many X-shifts one two-pass launch pair covers (0 = automatic). */
+typedef enum { HM_OPT_FORCE_PATH = 1, HM_OPT_BATCH_SHIFTS = 2 } hm_option;
+hm_status hm_set_option(hm_handle h, hm_option opt, int64_t value);
+
+/* ------------------------------------------------------------------------------------------ */
+/* Workspace sizes.  Each entry point needs a device workspace of at least the returned size.   */
+/* ------------------------------------------------------------------------------------------ */
+typedef enum {
+  HM_OP_SRE = 0,        /* hm_sre and hm_sre_partial (count ignored)                         */
+  HM_OP_SRE_ROWS = 1,   /* hm_sre_rows; count = n_rows                                       */
+  HM_OP_ROW_VALUES = 2, /* hm_sre_row_values (count ignored)                                 */
+  HM_OP_SRE_GRAD = 3,   /* hm_sre_grad (count ignored)                                       */
+  HM_OP_MANA = 4        /* hm_mana and hm_mana_partial (count ignored)                       */
+} hm_op;
+hm_status hm_workspace_size(hm_handle h, hm_op op, int n, hm_dtype dtype, int n_q, int64_t count,
+                            size_t *bytes);
+
+/* ------------------------------------------------------------------------------------------ */
+/* Qubits: stabilizer Renyi entropy (Eq. sre, Algorithm 2)                                     */
+/* ------------------------------------------------------------------------------------------ */
+/* out[0..n_q-1] = M_{q_i}(psi); out[n_q] = lost_norm = 1 - sum_P <P>^2 / 2^n.
+ * 1 <= n <= 26.  out: device, n_q + 1 doubles. */
+hm_status hm_sre(hm_handle h, const void *psi, int n, hm_dtype dtype, const double *q, int n_q,
+                 double *out, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Raw sums over the X-shifts a in [a0, a1) (sharding, checkpoint/resume):
+ *   sums[0] = sum_{a,b} |chi_b(a)|^2,
+ *   sums[1+i] = sum_{a,b} |chi_b(a)|^{2 q_i}   (q_i == 1: sum |chi|^2 log2 |chi|^2).
+ * Sums over disjoint ranges add up to the sums over their union.  0 <= a0 <= a1 <= 2^n.
+ * sums: device, n_q + 1 doubles (overwritten). */
+hm_status hm_sre_partial(hm_handle h, const void *psi, int n, hm_dtype dtype, const double *q,
+                         int n_q, uint64_t a0, uint64_t a1, double *sums, void *ws, size_t ws_bytes,
+                         hipStream_t stream);
+
+/* Turns raw sums (layout of hm_sre_partial, over all 2^n shifts) into out = {M_q..., lost_norm}
+ * (Eq. sre; the q -> 1 limit for q == 1).  sums, out: device. */
+hm_status hm_sre_finalize(int n, const double *q, int n_q, const double *sums, double *out,
+                          hipStream_t stream);
+
+/* Per-row sums for an explicit list of X-strings (the row evaluation of the sampling algorithm,
+ * Eq. feP, and of uniform-row Monte Carlo):
+ *   row_sums[r*(n_q+1) + 0] = sum_b |chi_b(rows[r])|^2,  row_sums[r*(n_q+1) + 1+i] = sum_b |chi_b|^{2 q_i}.
+ * rows: device array of n_rows uint64 values, each < 2^n (checked on the device: rows out of range
+ * give NaN row sums).  row_sums: device, n_rows * (n_q + 1) doubles. */
+hm_status hm_sre_rows(hm_handle h, const void *psi, int n, hm_dtype dtype, const uint64_t *rows,
+                      int64_t n_rows, const double *q, int n_q, double *row_sums, void *ws,
+                      size_t ws_bytes, hipStream_t stream);
+
+/* Signed real Pauli expectations of one X-row: out[b] = <psi|P_{a,b}|psi> for b in [0, 2^n), with
+ * P_{a,b} the Hermitian Pauli string whose qubit k carries I, X, Z, Y for (a_k, b_k) = (0,0), (1,0),
+ * (0,1), (1,1); i.e. out[b] = i^{popcount(a & b)} chi_b(a).  out: device, 2^n doubles.  n <= 26. */
+hm_status hm_sre_row_values(hm_handle h, const void *psi, int n, hm_dtype dtype, uint64_t a,
+                            double *out, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Fused forward + adjoint of M_q (q != 1): out = {M_q, lost_norm} (device, 2 doubles);
+ * grad = dM_q/dRe(psi) + i dM_q/dIm(psi) (torch's convention), same dtype and length as psi
+ * (device).  The adjoint differentiates chi_b(a) through Algorithm 2: with
+ * w_b(a) = |chi_b(a)|^{2q-2} chi_b(a), dS_q/dpsi*_y = 2q sum_a psi_{y XOR a} [H^{(x)n} w(a)]_y. */
+hm_status hm_sre_grad(hm_handle h, const void *psi, int n, hm_dtype dtype, double q, double *out,
+                      void *grad, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------------------------ */
+/* Qutrits: pure-state mana (Eq. mana2, Algorithm 4)                                            */
+/* ------------------------------------------------------------------------------------------ */
+/* out[0] = mana = log2(sum_u |<psi|A_u|psi>| / 3^n); out[1] = sum_u W(u) (= 1);
+ * out[2] = 3^n sum_u W(u)^2 (= 1 for a normalised pure state).  1 <= n <= 16.
+ * out: device, 3 doubles. */
+hm_status hm_mana(hm_handle h, const void *psi, int n, hm_dtype dtype, double *out, void *ws,
+                  size_t ws_bytes, hipStream_t stream);
+
+/* Raw sums over shifts a in [a0, a1) (a = sum_k a_k 3^k): sums = {sum |chi|, sum chi, sum chi^2}.
+ * sums: device, 3 doubles (overwritten).  0 <= a0 <= a1 <= 3^n. */
+hm_status hm_mana_partial(hm_handle h, const void *psi, int n, hm_dtype dtype, uint64_t a0,
+                          uint64_t a1, double *sums, void *ws, size_t ws_bytes, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HMAG_H */

@@ -1,0 +1,333 @@
+"""hmag -- numerically exact magic of state vectors on AMD MI355X (gfx950).
+
+Thin Python binding of libhmag.so (C-ABI declared in include/hmag.h).  This module only marshals
+arguments: torch supplies device memory and the current HIP stream; every step of the computation
+runs in the library's HIP kernels.  There is no CPU fallback -- if libhmag.so is missing or no GPU is
+visible the calls raise.
+
+Qubit states (d = 2) are complex64 / complex128 torch tensors of length 2^n on the GPU; qutrit
+states (d = 3) have length 3^n.  Digit k of the basis index is qudit k (little-endian).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import threading
+from typing import Sequence
+
+__all__ = [
+    "HmError", "lib", "lib_path", "Context", "default_context", "sre", "sre_partial", "sre_finalize",
+    "sre_rows", "sre_row_values", "sre_grad", "SRE", "mana", "mana_partial", "workspace_size",
+    "HM_C64", "HM_C128", "OP_SRE", "OP_SRE_ROWS", "OP_ROW_VALUES", "OP_SRE_GRAD", "OP_MANA",
+    "EXPORTED_SYMBOLS",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+lib_path = os.path.join(_HERE, "libhmag.so")
+
+HM_C64, HM_C128 = 0, 1
+OP_SRE, OP_SRE_ROWS, OP_ROW_VALUES, OP_SRE_GRAD, OP_MANA = 0, 1, 2, 3, 4
+OPT_FORCE_PATH, OPT_BATCH_SHIFTS = 1, 2
+
+_vp = ctypes.c_void_p
+_i = ctypes.c_int
+_i64 = ctypes.c_int64
+_u64 = ctypes.c_uint64
+_sz = ctypes.c_size_t
+_dp = ctypes.POINTER(ctypes.c_double)
+
+# name -> (restype, argtypes); this is also the list of symbols the header declares.
+_SIGS = {
+    "hm_create": (_i, [ctypes.POINTER(_vp)]),
+    "hm_destroy": (_i, [_vp]),
+    "hm_status_string": (ctypes.c_char_p, [_i]),
+    "hm_last_error": (ctypes.c_char_p, []),
+    "hm_version": (ctypes.c_char_p, []),
+    "hm_set_option": (_i, [_vp, _i, _i64]),
+    "hm_workspace_size": (_i, [_vp, _i, _i, _i, _i, _i64, ctypes.POINTER(_sz)]),
+    "hm_sre": (_i, [_vp, _vp, _i, _i, _dp, _i, _vp, _vp, _sz, _vp]),
+    "hm_sre_partial": (_i, [_vp, _vp, _i, _i, _dp, _i, _u64, _u64, _vp, _vp, _sz, _vp]),
+    "hm_sre_finalize": (_i, [_i, _dp, _i, _vp, _vp, _vp]),
+    "hm_sre_rows": (_i, [_vp, _vp, _i, _i, _vp, _i64, _dp, _i, _vp, _vp, _sz, _vp]),
+    "hm_sre_row_values": (_i, [_vp, _vp, _i, _i, _u64, _vp, _vp, _sz, _vp]),
+    "hm_sre_grad": (_i, [_vp, _vp, _i, _i, ctypes.c_double, _vp, _vp, _vp, _sz, _vp]),
+    "hm_mana": (_i, [_vp, _vp, _i, _i, _vp, _vp, _sz, _vp]),
+    "hm_mana_partial": (_i, [_vp, _vp, _i, _i, _u64, _u64, _vp, _vp, _sz, _vp]),
+}
+EXPORTED_SYMBOLS = tuple(_SIGS)
+
+_lib = None
+_lock = threading.Lock()
+
+
+class HmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(msg)
+        self.status = status
+
+
+def lib():
+    """Load libhmag.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        with _lock:
+            if _lib is None:
+                if not os.path.exists(lib_path):
+                    raise RuntimeError(f"{lib_path} is missing: build it with paper_2601_07824_amd.build.build()")
+                L = ctypes.CDLL(lib_path)
+                for name, (res, args) in _SIGS.items():
+                    f = getattr(L, name)
+                    f.restype = res
+                    f.argtypes = args
+                _lib = L
+    return _lib
+
+
+def _check(st: int):
+    if st != 0:
+        L = lib()
+        raise HmError(st, f"{L.hm_status_string(st).decode()}: {L.hm_last_error().decode()}")
+
+
+class Context:
+    """Owns one hm_handle (plans and options; no device memory)."""
+
+    def __init__(self):
+        h = _vp()
+        _check(lib().hm_create(ctypes.byref(h)))
+        self.h = h
+
+    def set_option(self, opt: int, value: int):
+        _check(lib().hm_set_option(self.h, opt, value))
+
+    def force_path(self, path: int):
+        self.set_option(OPT_FORCE_PATH, path)
+
+    def batch_shifts(self, b: int):
+        self.set_option(OPT_BATCH_SHIFTS, b)
+
+    def close(self):
+        if self.h:
+            lib().hm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default = None
+
+
+def default_context() -> Context:
+    global _default
+    if _default is None:
+        _default = Context()
+    return _default
+
+
+# ------------------------------------------------------------------------------------------------
+# marshalling helpers (torch is used only for memory and streams)
+# ------------------------------------------------------------------------------------------------
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.complex64:
+        return HM_C64
+    if t.dtype == torch.complex128:
+        return HM_C128
+    raise TypeError(f"state must be complex64 or complex128, got {t.dtype}")
+
+
+def _state(psi, d: int):
+    torch = _torch()
+    if not isinstance(psi, torch.Tensor) or not psi.is_cuda:
+        raise TypeError("state must be a torch tensor on the GPU")
+    if psi.dim() != 1:
+        raise ValueError("state must be one-dimensional")
+    psi = psi.contiguous()
+    D = psi.numel()
+    n = round(math.log(D, d)) if D > 0 else -1
+    if n < 1 or d ** n != D:
+        raise ValueError(f"state length {D} is not {d}^n with n >= 1")
+    return psi, n
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return _vp(s.cuda_stream)
+
+
+def _q(q) -> tuple:
+    qs = [float(x) for x in (q if isinstance(q, (list, tuple)) else [q])]
+    arr = (ctypes.c_double * len(qs))(*qs)
+    return arr, len(qs)
+
+
+def _ptr(t) -> _vp:
+    return _vp(t.data_ptr())
+
+
+def workspace_size(op: int, n: int, dtype_code: int, n_q: int = 1, count: int = 0, ctx: Context | None = None) -> int:
+    ctx = ctx or default_context()
+    b = _sz(0)
+    _check(lib().hm_workspace_size(ctx.h, op, n, dtype_code, n_q, count, ctypes.byref(b)))
+    return b.value
+
+
+def _workspace(nbytes: int, device):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+# ------------------------------------------------------------------------------------------------
+# qubits
+# ------------------------------------------------------------------------------------------------
+def sre(psi, q: Sequence[float] | float = (2.0,), *, ctx: Context | None = None, stream=None):
+    """[M_q for each q..., lost_norm] as a float64 tensor on the state's device."""
+    torch = _torch()
+    ctx = ctx or default_context()
+    psi, n = _state(psi, 2)
+    qa, nq = _q(q)
+    dt = _dtype_code(psi)
+    ws = _workspace(workspace_size(OP_SRE, n, dt, nq, 0, ctx), psi.device)
+    out = torch.empty(nq + 1, dtype=torch.float64, device=psi.device)
+    _check(lib().hm_sre(ctx.h, _ptr(psi), n, dt, qa, nq, _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
+    return out
+
+
+def sre_partial(psi, q=(2.0,), a0: int = 0, a1: int | None = None, *, ctx: Context | None = None, stream=None):
+    """Raw sums over X-shifts [a0, a1): [sum |chi|^2, sum |chi|^{2q}...] (float64 tensor)."""
+    torch = _torch()
+    ctx = ctx or default_context()
+    psi, n = _state(psi, 2)
+    a1 = (1 << n) if a1 is None else a1
+    qa, nq = _q(q)
+    dt = _dtype_code(psi)
+    ws = _workspace(workspace_size(OP_SRE, n, dt, nq, 0, ctx), psi.device)
+    out = torch.empty(nq + 1, dtype=torch.float64, device=psi.device)
+    _check(lib().hm_sre_partial(ctx.h, _ptr(psi), n, dt, qa, nq, a0, a1, _ptr(out), _ptr(ws), ws.numel(),
+                                _stream(stream)))
+    return out
+
+
+def sre_finalize(n: int, q, sums, *, stream=None):
+    torch = _torch()
+    qa, nq = _q(q)
+    out = torch.empty(nq + 1, dtype=torch.float64, device=sums.device)
+    sums = sums.contiguous()
+    _check(lib().hm_sre_finalize(n, qa, nq, _ptr(sums), _ptr(out), _stream(stream)))
+    return out
+
+
+def sre_rows(psi, rows, q=(2.0,), *, ctx: Context | None = None, stream=None):
+    """Per-row sums (n_rows, n_q + 1): [sum_b |chi_b(a)|^2, sum_b |chi_b(a)|^{2q}...] for a in rows."""
+    torch = _torch()
+    ctx = ctx or default_context()
+    psi, n = _state(psi, 2)
+    qa, nq = _q(q)
+    dt = _dtype_code(psi)
+    if not isinstance(rows, torch.Tensor):
+        rows = torch.as_tensor(rows, dtype=torch.int64)
+    rows = rows.to(device=psi.device, dtype=torch.int64).contiguous()
+    nr = rows.numel()
+    out = torch.empty((nr, nq + 1), dtype=torch.float64, device=psi.device)
+    ws = _workspace(workspace_size(OP_SRE_ROWS, n, dt, nq, nr, ctx), psi.device)
+    _check(lib().hm_sre_rows(ctx.h, _ptr(psi), n, dt, _ptr(rows), nr, qa, nq, _ptr(out), _ptr(ws), ws.numel(),
+                             _stream(stream)))
+    return out
+
+
+def sre_row_values(psi, a: int, *, ctx: Context | None = None, stream=None):
+    """<P_{a,b}> for b in [0, 2^n) (float64 tensor)."""
+    torch = _torch()
+    ctx = ctx or default_context()
+    psi, n = _state(psi, 2)
+    dt = _dtype_code(psi)
+    out = torch.empty(1 << n, dtype=torch.float64, device=psi.device)
+    ws = _workspace(workspace_size(OP_ROW_VALUES, n, dt, 1, 0, ctx), psi.device)
+    _check(lib().hm_sre_row_values(ctx.h, _ptr(psi), n, dt, int(a), _ptr(out), _ptr(ws), ws.numel(),
+                                   _stream(stream)))
+    return out
+
+
+def sre_grad(psi, q: float = 2.0, *, ctx: Context | None = None, stream=None):
+    """(tensor [M_q, lost_norm], grad = dM_q/dRe psi + i dM_q/dIm psi) in one fused call."""
+    torch = _torch()
+    ctx = ctx or default_context()
+    psi, n = _state(psi, 2)
+    dt = _dtype_code(psi)
+    out = torch.empty(2, dtype=torch.float64, device=psi.device)
+    grad = torch.empty_like(psi)
+    ws = _workspace(workspace_size(OP_SRE_GRAD, n, dt, 1, 0, ctx), psi.device)
+    _check(lib().hm_sre_grad(ctx.h, _ptr(psi), n, dt, float(q), _ptr(out), _ptr(grad), _ptr(ws), ws.numel(),
+                             _stream(stream)))
+    return out, grad
+
+
+def _make_autograd():
+    torch = _torch()
+
+    class SRE(torch.autograd.Function):
+        """M_q(psi) as a differentiable scalar; backward runs the fused forward + adjoint kernel."""
+
+        @staticmethod
+        def forward(ctx_, psi, q=2.0):
+            ctx_.save_for_backward(psi)
+            ctx_.q = float(q)
+            return sre(psi, (float(q),))[0]
+
+        @staticmethod
+        def backward(ctx_, g):
+            (psi,) = ctx_.saved_tensors
+            _, grad = sre_grad(psi, ctx_.q)
+            return grad * g.to(grad.real.dtype), None
+
+    return SRE
+
+
+class _LazySRE:
+    _cls = None
+
+    def __getattr__(self, item):
+        if _LazySRE._cls is None:
+            _LazySRE._cls = _make_autograd()
+        return getattr(_LazySRE._cls, item)
+
+
+SRE = _LazySRE()
+
+
+# ------------------------------------------------------------------------------------------------
+# qutrits
+# ------------------------------------------------------------------------------------------------
+def mana(psi, *, ctx: Context | None = None, stream=None):
+    """[mana, sum W, 3^n sum W^2] as a float64 tensor."""
+    torch = _torch()
+    ctx = ctx or default_context()
+    psi, n = _state(psi, 3)
+    dt = _dtype_code(psi)
+    out = torch.empty(3, dtype=torch.float64, device=psi.device)
+    ws = _workspace(workspace_size(OP_MANA, n, dt, 1, 0, ctx), psi.device)
+    _check(lib().hm_mana(ctx.h, _ptr(psi), n, dt, _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
+    return out
+
+
+def mana_partial(psi, a0: int = 0, a1: int | None = None, *, ctx: Context | None = None, stream=None):
+    torch = _torch()
+    ctx = ctx or default_context()
+    psi, n = _state(psi, 3)
+    a1 = 3 ** n if a1 is None else a1
+    dt = _dtype_code(psi)
+    out = torch.empty(3, dtype=torch.float64, device=psi.device)
+    ws = _workspace(workspace_size(OP_MANA, n, dt, 1, 0, ctx), psi.device)
+    _check(lib().hm_mana_partial(ctx.h, _ptr(psi), n, dt, a0, a1, _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
+    return out

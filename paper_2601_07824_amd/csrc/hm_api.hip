@@ -1,0 +1,295 @@
+// hm_api.hip -- the C-ABI of libhmag (include/hmag.h): argument validation, planning, workspace
+// sizing and dispatch to the gfx950 kernels.  Every check runs on the host before anything is
+// enqueued, so a failing call launches nothing and leaves its outputs untouched.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "../../include/hmag.h"
+#include "hm_internal.h"
+#include "hm_tile.h"
+
+#define HM_VERSION_STRING "hmag 0.1.0 (gfx950)"
+
+struct hm_context {
+  int force_path = 0;
+  int64_t batch_shifts = 0;
+};
+
+namespace hm {
+
+static thread_local char g_err[1024];
+
+int fail(int st, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+static int check_dtype(hm_dtype dt) {
+  if (dt != HM_C64 && dt != HM_C128) return fail(E_DTYPE, "dtype %d is neither HM_C64 nor HM_C128", (int)dt);
+  return OK;
+}
+
+static int check_ptr(const void *p, size_t align, const char *name) {
+  if (!p) return fail(E_ARG, "%s is NULL", name);
+  if ((uintptr_t)p % align) return fail(E_ALIGN, "%s = %p is not %zu-byte aligned", name, p, align);
+  return OK;
+}
+
+static int check_q(const double *q, int n_q, QArgs *qa) {
+  if (!q) return fail(E_ARG, "q is NULL");
+  if (n_q < 1 || n_q > HM_MAX_Q) return fail(E_ARG, "n_q = %d outside [1, %d]", n_q, HM_MAX_Q);
+  memset(qa, 0, sizeof(*qa));
+  qa->nq = n_q;
+  for (int i = 0; i < n_q; ++i) {
+    if (!(q[i] > 0.0) || !isfinite(q[i])) return fail(E_ARG, "q[%d] = %g must be positive and finite", i, q[i]);
+    qa->q[i] = q[i];
+  }
+  return OK;
+}
+
+static int check_ws(void *ws, size_t ws_bytes, size_t need) {
+  if (ws_bytes < need) return fail(E_WORKSPACE, "workspace of %zu bytes is smaller than the %zu bytes needed", ws_bytes, need);
+  if (need > 0) {
+    if (!ws) return fail(E_ARG, "ws is NULL but %zu bytes are needed", need);
+    if ((uintptr_t)ws % 256) return fail(E_ALIGN, "ws = %p is not 256-byte aligned", ws);
+  }
+  return OK;
+}
+
+static size_t psi_align(hm_dtype dt) { return dt == HM_C128 ? 16 : 8; }
+
+__global__ void k_fill(double *p, int64_t n, double v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+static int fill_dev(double *p, int64_t n, double v, hipStream_t st) {
+  if (n <= 0) return OK;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
+  return hipPeekAtLastError() == hipSuccess ? OK : fail(E_HIP, "fill launch: %s", hipGetErrorString(hipGetLastError()));
+}
+
+}  // namespace hm
+
+using namespace hm;
+
+#define HM_TRY(x)                          \
+  do {                                     \
+    int _s = (x);                          \
+    if (_s != OK) return (hm_status)_s;    \
+  } while (0)
+
+extern "C" {
+
+hm_status hm_create(hm_handle *h) {
+  g_err[0] = 0;
+  if (!h) return (hm_status)fail(E_ARG, "h is NULL");
+  *h = new (std::nothrow) hm_context();
+  if (!*h) return (hm_status)fail(E_ARG, "out of host memory");
+  return HM_OK;
+}
+
+hm_status hm_destroy(hm_handle h) {
+  delete h;
+  return HM_OK;
+}
+
+const char *hm_status_string(hm_status s) {
+  switch (s) {
+    case HM_OK: return "HM_OK";
+    case HM_E_ARG: return "HM_E_ARG: invalid argument";
+    case HM_E_DTYPE: return "HM_E_DTYPE: unsupported dtype";
+    case HM_E_SIZE: return "HM_E_SIZE: n outside the supported range";
+    case HM_E_WORKSPACE: return "HM_E_WORKSPACE: workspace too small";
+    case HM_E_UNSUPPORTED: return "HM_E_UNSUPPORTED: not implemented for these arguments";
+    case HM_E_HIP: return "HM_E_HIP: HIP runtime error";
+    case HM_E_ALIGN: return "HM_E_ALIGN: misaligned pointer";
+  }
+  return "unknown hm_status";
+}
+
+const char *hm_last_error(void) { return g_err; }
+const char *hm_version(void) { return HM_VERSION_STRING; }
+
+hm_status hm_set_option(hm_handle h, hm_option opt, int64_t value) {
+  if (!h) return (hm_status)fail(E_ARG, "h is NULL");
+  switch (opt) {
+    case HM_OPT_FORCE_PATH:
+      if (value < 0 || value > 2) return (hm_status)fail(E_ARG, "HM_OPT_FORCE_PATH %lld not in {0,1,2}", (long long)value);
+      h->force_path = (int)value;
+      return HM_OK;
+    case HM_OPT_BATCH_SHIFTS:
+      if (value < 0 || value > (1ll << 30)) return (hm_status)fail(E_ARG, "HM_OPT_BATCH_SHIFTS %lld out of range", (long long)value);
+      h->batch_shifts = value;
+      return HM_OK;
+  }
+  return (hm_status)fail(E_ARG, "unknown option %d", (int)opt);
+}
+
+hm_status hm_workspace_size(hm_handle h, hm_op op, int n, hm_dtype dtype, int n_q, int64_t count, size_t *bytes) {
+  g_err[0] = 0;
+  if (!h || !bytes) return (hm_status)fail(E_ARG, "h or bytes is NULL");
+  HM_TRY(check_dtype(dtype));
+  const int dbl = dtype == HM_C128;
+  switch (op) {
+    case HM_OP_SRE: {
+      if (n_q < 1 || n_q > HM_MAX_Q) return (hm_status)fail(E_ARG, "n_q = %d outside [1, %d]", n_q, HM_MAX_Q);
+      SrePlan p;
+      HM_TRY(sre_plan(n, dbl, h->force_path, h->batch_shifts, &p));
+      *bytes = sre_workspace(p, n_q, (int64_t)1 << n);
+      return HM_OK;
+    }
+    case HM_OP_SRE_ROWS: {
+      if (n_q < 1 || n_q > HM_MAX_Q) return (hm_status)fail(E_ARG, "n_q = %d outside [1, %d]", n_q, HM_MAX_Q);
+      if (count < 0) return (hm_status)fail(E_ARG, "count = %lld < 0", (long long)count);
+      SrePlan p;
+      HM_TRY(sre_plan(n, dbl, h->force_path, h->batch_shifts, &p));
+      *bytes = sre_workspace(p, n_q, 0);
+      return HM_OK;
+    }
+    case HM_OP_ROW_VALUES:
+      if (n < 1 || n > 26) return (hm_status)fail(E_SIZE, "row values: n = %d outside [1, 26]", n);
+      *bytes = sre_row_values_workspace(n, dbl);
+      return HM_OK;
+    case HM_OP_SRE_GRAD:
+      if (n < 1 || n > 24) return (hm_status)fail(E_SIZE, "gradient: n = %d outside [1, 24]", n);
+      *bytes = sre_grad_workspace(n, dbl);
+      return HM_OK;
+    case HM_OP_MANA: {
+      if (n < 1 || n > 16) return (hm_status)fail(E_SIZE, "mana: n = %d outside [1, 16]", n);
+      uint64_t D = 1;
+      for (int i = 0; i < n; ++i) D *= 3;
+      *bytes = mana_workspace(n, dbl, D);
+      return HM_OK;
+    }
+  }
+  return (hm_status)fail(E_ARG, "unknown op %d", (int)op);
+}
+
+hm_status hm_sre(hm_handle h, const void *psi, int n, hm_dtype dtype, const double *q, int n_q, double *out, void *ws,
+                 size_t ws_bytes, hipStream_t stream) {
+  g_err[0] = 0;
+  if (!h) return (hm_status)fail(E_ARG, "h is NULL");
+  HM_TRY(check_dtype(dtype));
+  HM_TRY(check_ptr(psi, psi_align(dtype), "psi"));
+  HM_TRY(check_ptr(out, 8, "out"));
+  QArgs qa;
+  HM_TRY(check_q(q, n_q, &qa));
+  SrePlan p;
+  HM_TRY(sre_plan(n, dtype == HM_C128, h->force_path, h->batch_shifts, &p));
+  const int64_t n_shifts = (int64_t)1 << n;
+  HM_TRY(check_ws(ws, ws_bytes, sre_workspace(p, n_q, n_shifts)));
+  return (hm_status)sre_run(p, psi, qa, 0, nullptr, n_shifts, nullptr, nullptr, out, ws, stream);
+}
+
+hm_status hm_sre_partial(hm_handle h, const void *psi, int n, hm_dtype dtype, const double *q, int n_q, uint64_t a0,
+                         uint64_t a1, double *sums, void *ws, size_t ws_bytes, hipStream_t stream) {
+  g_err[0] = 0;
+  if (!h) return (hm_status)fail(E_ARG, "h is NULL");
+  HM_TRY(check_dtype(dtype));
+  HM_TRY(check_ptr(psi, psi_align(dtype), "psi"));
+  HM_TRY(check_ptr(sums, 8, "sums"));
+  QArgs qa;
+  HM_TRY(check_q(q, n_q, &qa));
+  SrePlan p;
+  HM_TRY(sre_plan(n, dtype == HM_C128, h->force_path, h->batch_shifts, &p));
+  const uint64_t D = 1ull << n;
+  if (a0 > a1 || a1 > D) return (hm_status)fail(E_ARG, "shift range [%llu, %llu) not inside [0, 2^%d]", (unsigned long long)a0, (unsigned long long)a1, n);
+  const int64_t n_slots = (int64_t)(a1 - a0);
+  HM_TRY(check_ws(ws, ws_bytes, sre_workspace(p, n_q, n_slots)));
+  if (n_slots == 0) return (hm_status)fill_dev(sums, n_q + 1, 0.0, stream);
+  return (hm_status)sre_run(p, psi, qa, a0, nullptr, n_slots, nullptr, sums, nullptr, ws, stream);
+}
+
+hm_status hm_sre_finalize(int n, const double *q, int n_q, const double *sums, double *out, hipStream_t stream) {
+  g_err[0] = 0;
+  if (n < 1 || n > 62) return (hm_status)fail(E_SIZE, "n = %d outside [1, 62]", n);
+  HM_TRY(check_ptr(sums, 8, "sums"));
+  HM_TRY(check_ptr(out, 8, "out"));
+  QArgs qa;
+  HM_TRY(check_q(q, n_q, &qa));
+  return (hm_status)sre_finalize_launch(n, qa, sums, out, stream);
+}
+
+hm_status hm_sre_rows(hm_handle h, const void *psi, int n, hm_dtype dtype, const uint64_t *rows, int64_t n_rows,
+                      const double *q, int n_q, double *row_sums, void *ws, size_t ws_bytes, hipStream_t stream) {
+  g_err[0] = 0;
+  if (!h) return (hm_status)fail(E_ARG, "h is NULL");
+  HM_TRY(check_dtype(dtype));
+  HM_TRY(check_ptr(psi, psi_align(dtype), "psi"));
+  if (n_rows < 0) return (hm_status)fail(E_ARG, "n_rows = %lld < 0", (long long)n_rows);
+  QArgs qa;
+  HM_TRY(check_q(q, n_q, &qa));
+  SrePlan p;
+  HM_TRY(sre_plan(n, dtype == HM_C128, h->force_path, h->batch_shifts, &p));
+  if (n_rows == 0) return HM_OK;
+  HM_TRY(check_ptr(rows, 8, "rows"));
+  HM_TRY(check_ptr(row_sums, 8, "row_sums"));
+  HM_TRY(check_ws(ws, ws_bytes, sre_workspace(p, n_q, 0)));
+  return (hm_status)sre_run(p, psi, qa, 0, rows, n_rows, row_sums, nullptr, nullptr, ws, stream);
+}
+
+hm_status hm_sre_row_values(hm_handle h, const void *psi, int n, hm_dtype dtype, uint64_t a, double *out, void *ws,
+                            size_t ws_bytes, hipStream_t stream) {
+  g_err[0] = 0;
+  if (!h) return (hm_status)fail(E_ARG, "h is NULL");
+  HM_TRY(check_dtype(dtype));
+  if (n < 1 || n > 26) return (hm_status)fail(E_SIZE, "row values: n = %d outside [1, 26]", n);
+  HM_TRY(check_ptr(psi, psi_align(dtype), "psi"));
+  HM_TRY(check_ptr(out, 8, "out"));
+  if (a >> n) return (hm_status)fail(E_ARG, "a = %llu is not an %d-bit X-string", (unsigned long long)a, n);
+  HM_TRY(check_ws(ws, ws_bytes, sre_row_values_workspace(n, dtype == HM_C128)));
+  return (hm_status)sre_row_values_launch(n, dtype == HM_C128, psi, a, out, ws, stream);
+}
+
+hm_status hm_sre_grad(hm_handle h, const void *psi, int n, hm_dtype dtype, double q, double *out, void *grad, void *ws,
+                      size_t ws_bytes, hipStream_t stream) {
+  g_err[0] = 0;
+  if (!h) return (hm_status)fail(E_ARG, "h is NULL");
+  HM_TRY(check_dtype(dtype));
+  if (n < 1 || n > 24) return (hm_status)fail(E_SIZE, "gradient: n = %d outside [1, 24]", n);
+  HM_TRY(check_ptr(psi, psi_align(dtype), "psi"));
+  HM_TRY(check_ptr(grad, psi_align(dtype), "grad"));
+  HM_TRY(check_ptr(out, 8, "out"));
+  if (!(q > 0.0) || !isfinite(q) || q == 1.0) return (hm_status)fail(E_ARG, "gradient: q = %g must be positive, finite and != 1", q);
+  HM_TRY(check_ws(ws, ws_bytes, sre_grad_workspace(n, dtype == HM_C128)));
+  return (hm_status)sre_grad_launch(n, dtype == HM_C128, psi, q, out, grad, ws, ws_bytes, stream);
+}
+
+hm_status hm_mana(hm_handle h, const void *psi, int n, hm_dtype dtype, double *out, void *ws, size_t ws_bytes,
+                  hipStream_t stream) {
+  g_err[0] = 0;
+  if (!h) return (hm_status)fail(E_ARG, "h is NULL");
+  HM_TRY(check_dtype(dtype));
+  if (n < 1 || n > 16) return (hm_status)fail(E_SIZE, "mana: n = %d outside [1, 16]", n);
+  HM_TRY(check_ptr(psi, psi_align(dtype), "psi"));
+  HM_TRY(check_ptr(out, 8, "out"));
+  uint64_t D = 1;
+  for (int i = 0; i < n; ++i) D *= 3;
+  HM_TRY(check_ws(ws, ws_bytes, mana_workspace(n, dtype == HM_C128, D)));
+  return (hm_status)mana_launch(n, dtype == HM_C128, psi, 0, D, nullptr, out, ws, ws_bytes, stream);
+}
+
+hm_status hm_mana_partial(hm_handle h, const void *psi, int n, hm_dtype dtype, uint64_t a0, uint64_t a1, double *sums,
+                          void *ws, size_t ws_bytes, hipStream_t stream) {
+  g_err[0] = 0;
+  if (!h) return (hm_status)fail(E_ARG, "h is NULL");
+  HM_TRY(check_dtype(dtype));
+  if (n < 1 || n > 16) return (hm_status)fail(E_SIZE, "mana: n = %d outside [1, 16]", n);
+  HM_TRY(check_ptr(psi, psi_align(dtype), "psi"));
+  HM_TRY(check_ptr(sums, 8, "sums"));
+  uint64_t D = 1;
+  for (int i = 0; i < n; ++i) D *= 3;
+  if (a0 > a1 || a1 > D) return (hm_status)fail(E_ARG, "shift range [%llu, %llu) not inside [0, 3^%d]", (unsigned long long)a0, (unsigned long long)a1, n);
+  HM_TRY(check_ws(ws, ws_bytes, mana_workspace(n, dtype == HM_C128, a1 - a0)));
+  if (a1 == a0) return (hm_status)fill_dev(sums, 3, 0.0, stream);
+  return (hm_status)mana_launch(n, dtype == HM_C128, psi, a0, a1, sums, nullptr, ws, ws_bytes, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,160 @@
+// hm_tile.h -- device building blocks shared by the gfx950 kernels of libhmag.
+//
+// A "tile" is 2^TB complex values held by NT = 2^LT threads of one workgroup, R = 2^RB values per
+// thread in registers.  A round layout with start S places the register index bits at tile-index
+// positions [S, S+RB) and the thread index bits at the remaining positions, in order:
+//     idx = (tau & (2^S - 1)) | (rho << S) | ((tau >> S) << (S + RB)).
+// Butterflies act on register bits; moving to a layout with another S is one pass through LDS.
+// LDS addresses are padded with one slot per R values (phys = idx + idx/R): for every layout above,
+// any 32 consecutive lanes (8-byte values) or 16 lanes (16-byte values) then hit distinct banks, and
+// the per-register part of the address stays a compile-time constant.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hm_internal.h"
+
+namespace hm {
+
+template <typename T> struct vec2_of;
+template <> struct vec2_of<float> { using type = float2; };
+template <> struct vec2_of<double> { using type = double2; };
+template <typename T> using vec2 = typename vec2_of<T>::type;
+
+__host__ __device__ constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x >> 1); }
+
+template <int S, int RB>
+__device__ __forceinline__ uint32_t lay(uint32_t tau, uint32_t rho) {
+  return (tau & ((1u << S) - 1u)) | (rho << S) | ((tau >> S) << (S + RB));
+}
+
+template <int RB>
+__device__ __forceinline__ uint32_t ldspad(uint32_t idx) { return idx + (idx >> RB); }
+
+// insert a zero bit at position j: bits >= j move up by one.
+__device__ __forceinline__ uint64_t ins0(uint64_t c, int j) {
+  uint64_t lo = c & ((1ull << j) - 1ull);
+  return lo | ((c - lo) << 1);
+}
+__device__ __forceinline__ uint32_t ins0_32(uint32_t c, int j) {
+  uint32_t lo = c & ((1u << j) - 1u);
+  return lo | ((c - lo) << 1);
+}
+
+// Unnormalised Walsh-Hadamard butterflies over register bits [K0, K1).
+template <typename T, int R, int K0, int K1>
+__device__ __forceinline__ void wht_regs(T (&re)[R], T (&im)[R]) {
+#pragma unroll
+  for (int k = K0; k < K1; ++k) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      if (!((i >> k) & 1)) {
+        const int j = i | (1 << k);
+        T a = re[i], b = re[j];
+        re[i] = a + b;
+        re[j] = a - b;
+        a = im[i];
+        b = im[j];
+        im[i] = a + b;
+        im[j] = a - b;
+      }
+    }
+  }
+}
+
+// Move the tile from layout SA to layout SB through LDS (all NT threads must call it).
+template <typename T, int R, int RB, int SA, int SB>
+__device__ __forceinline__ void relayout(T (&re)[R], T (&im)[R], vec2<T> *lds, uint32_t tau) {
+  __syncthreads();  // earlier readers of lds are done
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    vec2<T> v;
+    v.x = re[r];
+    v.y = im[r];
+    lds[ldspad<RB>(lay<SA, RB>(tau, (uint32_t)r))] = v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    vec2<T> v = lds[ldspad<RB>(lay<SB, RB>(tau, (uint32_t)r))];
+    re[r] = v.x;
+    im[r] = v.y;
+  }
+}
+
+// Deterministic sum over aligned segments of SEG consecutive threads (SEG a power of two dividing
+// NT).  Returns the segment total in the first thread of each segment (other threads: partial).
+// lds must hold NT/64 doubles per value.
+template <int NT, int SEG>
+__device__ __forceinline__ double seg_sum(double v, double *lds, uint32_t tau) {
+  constexpr int WSEG = SEG < 64 ? SEG : 64;
+#pragma unroll
+  for (int off = 1; off < WSEG; off <<= 1) v += __shfl_xor(v, off, 64);
+  if constexpr (SEG > 64) {
+    constexpr int NW = SEG / 64;
+    __syncthreads();
+    if ((tau & 63u) == 0) lds[tau >> 6] = v;
+    __syncthreads();
+    if ((tau & (SEG - 1)) == 0) {
+      double s = 0.0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) s += lds[(tau >> 6) + w];
+      v = s;
+    }
+  }
+  return v;
+}
+
+// Arguments describing the Renyi indices of one call (passed by value to kernels).
+struct QArgs {
+  int nq;
+  double q[HM_MAX_Q];
+};
+
+// Per-real-value accumulation of the reduction of Algorithm 2: t = x^2 = |<P>|^2 (folded form),
+// acc[0] += t, acc[1+i] += t^{q_i} (q_i == 1: t log2 t).
+template <typename T, int QM> struct Acc {
+  static constexpr int N = (QM == 2) ? 2 : HM_MAX_Q + 1;
+  T a[N];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int i = 0; i < N; ++i) a[i] = T(0);
+  }
+  __device__ __forceinline__ void add(T x, const QArgs &qa) {
+    const T t = x * x;
+    a[0] += t;
+    if constexpr (QM == 2) {
+      a[1] = __builtin_fma(t, t, a[1]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < HM_MAX_Q; ++i) {
+        if (i < qa.nq) {
+          const double q = qa.q[i];
+          T v;
+          if (q == 1.0) v = t > T(0) ? t * (T)log2(t) : T(0);
+          else if (q == 2.0) v = t * t;
+          else if (q == 3.0) v = t * t * t;
+          else if (q == 4.0) { T t2 = t * t; v = t2 * t2; }
+          else v = t > T(0) ? (T)pow(t, (T)q) : T(0);
+          a[1 + i] += v;
+        }
+      }
+    }
+  }
+};
+
+// Scale folded per-shift sums to the unfolded convention: a != 0 shifts were folded on one bit,
+// |chi|^2 = f t with f = 4; the a == 0 shift is folded without the factor (f = 1).
+__device__ __forceinline__ void unfold_scale(double *s, int nacc, const QArgs &qa, bool a_is_zero) {
+  if (a_is_zero) return;
+  const double f = 4.0;
+  const double s0 = s[0];
+  s[0] = f * s0;
+  for (int i = 0; i < qa.nq && 1 + i < nacc; ++i) {
+    const double q = qa.q[i];
+    if (q == 1.0) s[1 + i] = f * (s[1 + i] + 2.0 * s0);  // f (sum t log2 t + log2(f) sum t)
+    else s[1 + i] = exp2(2.0 * q) * s[1 + i];
+  }
+}
+
+}  // namespace hm

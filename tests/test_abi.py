@@ -1,0 +1,120 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function include/hmag.h declares,
+and rejects invalid arguments synchronously on the host (nothing is launched on error, so fake
+device pointers are safe in these cases)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2601_07824_amd as hm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hmag.h")
+
+HM_OK, HM_E_ARG, HM_E_DTYPE, HM_E_SIZE, HM_E_WORKSPACE, HM_E_UNSUPPORTED, HM_E_HIP, HM_E_ALIGN = range(8)
+P = ctypes.c_void_p
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hm_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    return hm.lib()
+
+
+@pytest.fixture(scope="module")
+def h(L):
+    hh = P()
+    assert L.hm_create(ctypes.byref(hh)) == HM_OK
+    yield hh
+    L.hm_destroy(hh)
+
+
+def test_every_declared_symbol_is_exported_and_bound(L):
+    decl = declared_functions()
+    assert decl, "no declarations parsed"
+    for name in decl:
+        assert hasattr(L, name), name
+    assert sorted(hm.EXPORTED_SYMBOLS) == decl
+
+
+def test_version_and_status_strings(L):
+    assert b"gfx950" in L.hm_version()
+    for s in range(8):
+        assert L.hm_status_string(s).startswith(b"HM_")
+
+
+def q_arr(*q):
+    return (ctypes.c_double * len(q))(*q)
+
+
+def test_sre_argument_errors(L, h):
+    q = q_arr(2.0)
+    good = P(0x100000)  # never dereferenced: every call below fails validation first
+    ws = P(0x200000)
+    assert L.hm_sre(None, good, 8, 0, q, 1, good, ws, 1 << 30, None) == HM_E_ARG
+    assert L.hm_sre(h, None, 8, 0, q, 1, good, ws, 1 << 30, None) == HM_E_ARG
+    assert b"psi" in L.hm_last_error()
+    assert L.hm_sre(h, good, 8, 7, q, 1, good, ws, 1 << 30, None) == HM_E_DTYPE
+    assert L.hm_sre(h, good, 0, 0, q, 1, good, ws, 1 << 30, None) == HM_E_SIZE
+    assert L.hm_sre(h, good, 27, 0, q, 1, good, ws, 1 << 30, None) == HM_E_SIZE
+    assert L.hm_sre(h, good, 8, 0, q_arr(-1.0), 1, good, ws, 1 << 30, None) == HM_E_ARG
+    assert L.hm_sre(h, good, 8, 0, q_arr(float("nan")), 1, good, ws, 1 << 30, None) == HM_E_ARG
+    assert L.hm_sre(h, good, 8, 0, q, 0, good, ws, 1 << 30, None) == HM_E_ARG
+    assert L.hm_sre(h, good, 8, 0, q, 9, good, ws, 1 << 30, None) == HM_E_ARG
+    assert L.hm_sre(h, P(0x100004), 8, 0, q, 1, good, ws, 1 << 30, None) == HM_E_ALIGN
+    assert L.hm_sre(h, P(0x100008), 8, 1, q, 1, good, ws, 1 << 30, None) == HM_E_ALIGN  # c128 needs 16 B
+    assert L.hm_sre(h, good, 8, 0, q, 1, good, P(0x200010), 1 << 30, None) == HM_E_ALIGN
+    assert L.hm_sre(h, good, 8, 0, q, 1, good, ws, 16, None) == HM_E_WORKSPACE
+    assert b"workspace" in L.hm_last_error()
+
+
+def test_partial_rows_and_values_errors(L, h):
+    q = q_arr(2.0)
+    good, ws = P(0x100000), P(0x200000)
+    assert L.hm_sre_partial(h, good, 8, 0, q, 1, 5, 3, good, ws, 1 << 30, None) == HM_E_ARG
+    assert L.hm_sre_partial(h, good, 8, 0, q, 1, 0, 257, good, ws, 1 << 30, None) == HM_E_ARG
+    assert L.hm_sre_rows(h, good, 8, 0, good, -1, q, 1, good, ws, 1 << 30, None) == HM_E_ARG
+    assert L.hm_sre_rows(h, good, 8, 0, None, 4, q, 1, good, ws, 1 << 30, None) == HM_E_ARG
+    assert L.hm_sre_row_values(h, good, 8, 0, 256, good, ws, 1 << 30, None) == HM_E_ARG
+    assert L.hm_sre_row_values(h, good, 8, 0, 3, good, ws, 8, None) == HM_E_WORKSPACE
+    assert L.hm_sre_grad(h, good, 8, 0, 1.0, good, good, ws, 1 << 30, None) == HM_E_ARG
+    assert L.hm_sre_grad(h, good, 8, 0, 2.0, good, None, ws, 1 << 30, None) == HM_E_ARG
+    assert L.hm_mana(h, good, 0, 0, good, ws, 1 << 30, None) == HM_E_SIZE
+    assert L.hm_mana_partial(h, good, 4, 0, 0, 82, good, ws, 1 << 30, None) == HM_E_ARG
+    assert L.hm_sre_finalize(8, q, 1, None, good, None) == HM_E_ARG
+
+
+def test_options_and_forced_paths(L, h):
+    hh = P()
+    assert L.hm_create(ctypes.byref(hh)) == HM_OK
+    try:
+        assert L.hm_set_option(hh, 1, 3) == HM_E_ARG
+        assert L.hm_set_option(hh, 99, 0) == HM_E_ARG
+        b = ctypes.c_size_t()
+        assert L.hm_set_option(hh, 1, 2) == HM_OK  # two-pass needs n >= 11 for c64
+        assert L.hm_workspace_size(hh, 0, 8, 0, 1, 0, ctypes.byref(b)) == HM_E_UNSUPPORTED
+        assert L.hm_workspace_size(hh, 0, 16, 0, 1, 0, ctypes.byref(b)) == HM_OK
+        assert L.hm_set_option(hh, 1, 1) == HM_OK  # workgroup-resident holds at most 2^13 folded c64 values
+        assert L.hm_workspace_size(hh, 0, 16, 0, 1, 0, ctypes.byref(b)) == HM_E_UNSUPPORTED
+        assert L.hm_workspace_size(hh, 0, 14, 0, 1, 0, ctypes.byref(b)) == HM_OK
+    finally:
+        L.hm_destroy(hh)
+
+
+def test_workspace_sizes(L, h):
+    b = ctypes.c_size_t()
+    prev = 0
+    for n in range(1, 23):
+        assert L.hm_workspace_size(h, 0, n, 0, 1, 0, ctypes.byref(b)) == HM_OK
+        assert b.value >= 16 * (1 << n) and b.value % 256 == 0
+        assert b.value >= prev
+        prev = b.value
+    assert L.hm_workspace_size(h, 0, 8, 5, 1, 0, ctypes.byref(b)) == HM_E_DTYPE
+    assert L.hm_workspace_size(h, 1, 20, 0, 1, 4096, ctypes.byref(b)) == HM_OK
+    assert L.hm_workspace_size(h, 2, 20, 1, 1, 0, ctypes.byref(b)) == HM_OK and b.value >= 16 << 20

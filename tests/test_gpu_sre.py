@@ -1,0 +1,221 @@
+"""GPU parity of the qubit SRE kernels against the FP64 oracle, through the C-ABI.
+
+Tolerances: FP64 transforms (complex128 input) <= 1e-10 relative (absolute when the reference is 0);
+FP32 transforms (complex64 input) <= 1e-5 relative on M_q (absolute 1e-5 when the reference is 0).
+Complex64 runs are compared with the oracle evaluated on the same complex64 values widened to
+complex128, so both sides see identical inputs.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from synth import states as S
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def hm():
+    import paper_2601_07824_amd as m
+    m.lib()
+    return m
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rel_err(got, want, floor=1.0):
+    got, want = np.asarray(got, dtype=float), np.asarray(want, dtype=float)
+    return np.max(np.abs(got - want) / np.maximum(np.abs(want), floor))
+
+
+def gpu_state(psi, c64: bool):
+    if c64:
+        v, w = S.to_c64_exact(psi)
+        return torch.from_numpy(v).to(_dev()), w
+    return torch.from_numpy(psi).to(_dev()), psi
+
+
+TOL = {False: 1e-10, True: 1e-5}
+
+
+# ---------------------------------------------------------------------------------------------
+# Qubit SRE, N = 8: the small configuration (M_1, M_2, M_3, all 256 shifts)
+# ---------------------------------------------------------------------------------------------
+def n8_states():
+    g = np.random.default_rng(1008)
+    th, ph = g.uniform(0, math.pi, 8), g.uniform(0, 2 * math.pi, 8)
+    out = [("gauss%d" % s, S.gaussian_state(8, seed=1000 + s)) for s in range(4)]
+    out += [("zero", S.zero_state(8)), ("ghz", S.ghz_state(8)), ("product", S.qubit_product_state(th, ph))]
+    return out
+
+
+@pytest.mark.parametrize("c64", [False, True])
+def test_n8_vs_direct_oracle(orc, hm, c64):
+    q = (1.0, 2.0, 3.0)
+    for name, psi in n8_states():
+        say(f"[sre n8] state={name} c64={c64}")
+        x, w = gpu_state(psi, c64)
+        got = hm.sre(x, q).cpu().numpy()
+        want = orc.sre_direct(w, q)
+        assert rel_err(got[:3], want[:3]) < TOL[c64], (name, got, want)
+        assert abs(got[3] - want[3]) < (1e-12 if not c64 else 1e-6), (name, got, want)
+
+
+# ---------------------------------------------------------------------------------------------
+# All sizes and both kernel families vs Algorithm 2 on the CPU
+# ---------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("c64", [False, True])
+@pytest.mark.parametrize("n", list(range(1, 14)))
+def test_sizes_auto_path(orc, hm, n, c64):
+    q = (2.0,) if n % 2 else (1.0, 2.0, 3.0, 0.5)
+    psi = S.gaussian_state(n, seed=2000 + n)
+    say(f"[sre sizes] n={n} c64={c64} q={q}")
+    x, w = gpu_state(psi, c64)
+    got = hm.sre(x, q).cpu().numpy()
+    want = orc.sre_fwht(w, q)
+    assert rel_err(got[:-1], want[:-1]) < TOL[c64], (got, want)
+    assert abs(got[-1] - want[-1]) < (1e-12 if not c64 else 2e-6)
+
+
+@pytest.mark.parametrize("c64,n", [(False, 11), (False, 12), (False, 13), (True, 12), (True, 13), (True, 14)])
+def test_forced_two_pass(orc, hm, n, c64):
+    """Two-pass kernels at sizes the oracle finishes quickly; batch of 5 shifts -> ragged last batch."""
+    ctx = hm.Context()
+    ctx.force_path(2)
+    ctx.batch_shifts(5)
+    psi = S.brickwall_haar(n, 2 * n, seed=3000 + n)
+    for q in ((2.0,), (1.0, 2.0, 3.0)):
+        say(f"[sre two-pass] n={n} c64={c64} q={q}")
+        x, w = gpu_state(psi, c64)
+        got = hm.sre(x, q, ctx=ctx).cpu().numpy()
+        want = orc.sre_fwht(w, q)
+        assert rel_err(got[:-1], want[:-1]) < TOL[c64], (got, want)
+
+
+@pytest.mark.parametrize("c64", [False, True])
+def test_workgroup_resident_largest(orc, hm, c64):
+    n = 13 if c64 else 12
+    ctx = hm.Context()
+    ctx.force_path(1)
+    psi = S.gaussian_state(n, seed=3100)
+    say(f"[sre resident max] n={n} c64={c64}")
+    x, w = gpu_state(psi, c64)
+    got = hm.sre(x, (2.0,), ctx=ctx).cpu().numpy()
+    want = orc.sre_fwht(w, (2.0,))
+    assert rel_err(got[:1], want[:1]) < TOL[c64]
+
+
+@pytest.mark.parametrize("c64", [False, True])
+def test_partial_ranges_add_up(orc, hm, c64):
+    """hm_sre_partial on ragged ranges equals the oracle's sums over the same ranges."""
+    n = 10
+    psi = S.gaussian_state(n, seed=3200)
+    x, w = gpu_state(psi, c64)
+    q = (2.0, 3.0)
+    cuts = [0, 1, 2, 37, 511, 512, 513, 1000, 1024]
+    for a0, a1 in zip(cuts[:-1], cuts[1:]):
+        say(f"[sre partial] range=[{a0},{a1}) c64={c64}")
+        got = hm.sre_partial(x, q, a0, a1).cpu().numpy()
+        want = orc.sre_fwht_sums(w, q, a0, a1)
+        assert rel_err(got, want, floor=1e-300) < (1e-11 if not c64 else 2e-6), (a0, a1, got, want)
+    say("[sre partial] empty range")
+    assert np.all(hm.sre_partial(x, q, 7, 7).cpu().numpy() == 0)
+
+
+@pytest.mark.parametrize("path", [1, 2])
+@pytest.mark.parametrize("c64", [False, True])
+def test_rows_vs_oracle(orc, hm, path, c64):
+    n = 12
+    ctx = hm.Context()
+    ctx.force_path(path)
+    ctx.batch_shifts(7)
+    psi = S.gaussian_state(n, seed=3300)
+    rows = np.concatenate([[0, 1, 2 ** n - 1, 2 ** (n - 1), 5, 5], S.uniform_rows(n, 40, seed=3301)]).astype(np.int64)
+    x, w = gpu_state(psi, c64)
+    say(f"[sre rows] n={n} path={path} c64={c64} rows={len(rows)}")
+    got = hm.sre_rows(x, rows, (2.0,), ctx=ctx).cpu().numpy()
+    want = orc.sre_rows(w, rows.astype(np.uint64), (2.0,))
+    assert rel_err(got, want, floor=1e-12) < (1e-11 if not c64 else 2e-6)
+
+
+def test_rows_out_of_range_give_nan(hm):
+    n = 9
+    x = torch.from_numpy(S.gaussian_state(n, seed=1)).to(_dev())
+    say("[sre rows] out-of-range row")
+    got = hm.sre_rows(x, [3, 2 ** n, 4], (2.0,)).cpu().numpy()
+    assert np.all(np.isnan(got[1])) and np.all(np.isfinite(got[[0, 2]]))
+
+
+@pytest.mark.parametrize("c64", [False, True])
+def test_row_values_vs_oracle(orc, hm, c64):
+    n = 9
+    psi = S.gaussian_state(n, seed=3400)
+    x, w = gpu_state(psi, c64)
+    for a in (0, 1, 300, 511):
+        say(f"[sre row values] a={a} c64={c64}")
+        got = hm.sre_row_values(x, a).cpu().numpy()
+        want, _ = orc.sre_row_values_fwht(w, a)
+        assert np.max(np.abs(got - want)) < (1e-13 if not c64 else 1e-6)
+
+
+def test_determinism_bitwise(hm):
+    for n, c64 in ((12, True), (15, True), (11, False)):
+        x, _ = gpu_state(S.gaussian_state(n, seed=3500), c64)
+        say(f"[sre determinism] n={n} c64={c64}")
+        a = hm.sre(x, (2.0, 3.0)).cpu().numpy()
+        b = hm.sre(x, (2.0, 3.0)).cpu().numpy()
+        assert np.array_equal(a, b)
+
+
+# ---------------------------------------------------------------------------------------------
+# Full sizes: properties that hold at any N, and sampled rows against the oracle
+# ---------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [16, 20])
+def test_full_size_stabilizer_and_t_states(hm, n):
+    """Random Clifford circuits give M_2 = 0; Clifford images of (T|+>)^k give k log2(4/3) exactly."""
+    for c64 in (True, False):
+        for k in (0, 1, 4):
+            psi = S.t_plus_clifford_state(n, k, seed=4000 + n + k, layers=2 * n)
+            x, _ = gpu_state(psi, c64)
+            say(f"[sre full] n={n} k={k} c64={c64}")
+            got = hm.sre(x, (2.0,)).cpu().numpy()
+            want = k * math.log2(4 / 3)
+            tol = 1e-5 * max(want, 1.0) if c64 else 1e-9
+            assert abs(got[0] - want) < tol, (got, want)
+            assert abs(got[1]) < (1e-5 if c64 else 1e-10)
+
+
+@pytest.mark.parametrize("n", [16, 20])
+def test_full_size_sampled_rows(orc, hm, n):
+    """Per-row sums of the launch configuration used for the full N (two-pass) vs the oracle."""
+    psi = S.brickwall_haar(n, 2 * n, seed=4100 + n)
+    rows = np.concatenate([[0, 1, 2 ** n - 1], S.uniform_rows(n, 13, seed=4101)]).astype(np.int64)
+    for c64 in (True, False):
+        x, w = gpu_state(psi, c64)
+        say(f"[sre full rows] n={n} c64={c64}")
+        got = hm.sre_rows(x, rows, (2.0,)).cpu().numpy()
+        want = orc.sre_rows(w, rows.astype(np.uint64), (2.0,))
+        assert rel_err(got, want, floor=1e-15) < (1e-10 if not c64 else 1e-5)
+
+
+def test_full_size_n16_vs_oracle(orc, hm):
+    """N = 16 complex64 (two-pass) against the full FP64 oracle."""
+    n = 16
+    psi = S.brickwall_haar(n, 2 * n, seed=4200)
+    x, w = gpu_state(psi, True)
+    say("[sre n16 full] c64")
+    got = hm.sre(x, (2.0,)).cpu().numpy()
+    want = orc.sre_fwht(w, (2.0,))
+    assert rel_err(got[:1], want[:1]) < 1e-5
+    assert abs(got[1] - want[1]) < 1e-5
