@@ -146,6 +146,20 @@ hm_status hm_mana(hm_handle h, const void *psi, int n, hm_dtype dtype, double *o
 hm_status hm_mana_partial(hm_handle h, const void *psi, int n, hm_dtype dtype, uint64_t a0,
                           uint64_t a1, double *sums, void *ws, size_t ws_bytes, hipStream_t stream);
 
+
+/* ------------------------------------------------------------------------------------------ */
+/* Kernel timing (diagnostics)                                                                 */
+/* ------------------------------------------------------------------------------------------ */
+/* While enabled, each kernel launch is bracketed by hipEvents recorded on its stream.  Off by
+ * default; process-wide. */
+hm_status hm_profile_enable(int on);
+/* Drops the accumulated timings. */
+hm_status hm_profile_reset(void);
+/* Timing of kernel family `index` (0-based, in order of first launch): its name (NUL-terminated,
+ * truncated to name_len), number of launches and summed device milliseconds.  Synchronises with
+ * the recorded events.  HM_E_ARG once index passes the last family. */
+hm_status hm_profile_query(int index, char *name, size_t name_len, int64_t *count, double *ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -19,7 +19,7 @@ from typing import Sequence
 __all__ = [
     "HmError", "lib", "lib_path", "Context", "default_context", "sre", "sre_partial", "sre_finalize",
     "sre_rows", "sre_row_values", "sre_grad", "SRE", "mana", "mana_partial", "workspace_size",
-    "HM_C64", "HM_C128", "OP_SRE", "OP_SRE_ROWS", "OP_ROW_VALUES", "OP_SRE_GRAD", "OP_MANA",
+    "HM_C64", "HM_C128", "profile_enable", "profile_reset", "profile_read", "OP_SRE", "OP_SRE_ROWS", "OP_ROW_VALUES", "OP_SRE_GRAD", "OP_MANA",
     "EXPORTED_SYMBOLS",
 ]
 
@@ -54,6 +54,9 @@ _SIGS = {
     "hm_sre_grad": (_i, [_vp, _vp, _i, _i, ctypes.c_double, _vp, _vp, _vp, _sz, _vp]),
     "hm_mana": (_i, [_vp, _vp, _i, _i, _vp, _vp, _sz, _vp]),
     "hm_mana_partial": (_i, [_vp, _vp, _i, _i, _u64, _u64, _vp, _vp, _sz, _vp]),
+    "hm_profile_enable": (_i, [_i]),
+    "hm_profile_reset": (_i, []),
+    "hm_profile_query": (_i, [_i, ctypes.c_char_p, _sz, ctypes.POINTER(_i64), _dp]),
 }
 EXPORTED_SYMBOLS = tuple(_SIGS)
 
@@ -186,6 +189,30 @@ def workspace_size(op: int, n: int, dtype_code: int, n_q: int = 1, count: int = 
 def _workspace(nbytes: int, device):
     torch = _torch()
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def profile_enable(on: bool = True):
+    """Bracket every library kernel launch with hipEvents on its stream (see hm_profile_enable)."""
+    _check(lib().hm_profile_enable(1 if on else 0))
+
+
+def profile_reset():
+    _check(lib().hm_profile_reset())
+
+
+def profile_read() -> dict:
+    """{kernel family: (launches, total device ms)} accumulated since the last reset."""
+    out = {}
+    i = 0
+    buf = ctypes.create_string_buffer(128)
+    while True:
+        c, ms = _i64(0), ctypes.c_double(0.0)
+        st = lib().hm_profile_query(i, buf, 128, ctypes.byref(c), ctypes.byref(ms))
+        if st != 0:
+            break
+        out[buf.value.decode()] = (c.value, ms.value)
+        i += 1
+    return out
 
 
 # ------------------------------------------------------------------------------------------------

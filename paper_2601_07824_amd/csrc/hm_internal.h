@@ -18,6 +18,16 @@ enum Status { OK = 0, E_ARG = 1, E_DTYPE = 2, E_SIZE = 3, E_WORKSPACE = 4, E_UNS
 // Records a formatted message for hm_last_error() and returns st.
 int fail(int st, const char *fmt, ...);
 
+// Kernel timing hooks (hm_profile_*): bracket a launch on stream st.
+void *prof_begin(const char *name, hipStream_t st);
+void prof_end(void *tok, hipStream_t st);
+struct ProfScope {
+  void *tok;
+  hipStream_t st;
+  ProfScope(const char *name, hipStream_t s) : tok(prof_begin(name, s)), st(s) {}
+  ~ProfScope() { prof_end(tok, st); }
+};
+
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 // ---- SRE forward -----------------------------------------------------------------------------

@@ -1,0 +1,107 @@
+// hm_profile.hip -- optional per-kernel-family timing with HIP events on the launch stream.
+//
+// When enabled (hm_profile_enable(1)), every kernel launch of the library is bracketed by two
+// hipEventRecord calls on the stream it is enqueued on; hm_profile_query() synchronises on the
+// recorded events and reports, per kernel family, the number of launches and the summed
+// event-to-event device time.  Disabled by default; costs nothing when disabled.
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/hmag.h"
+#include "hm_internal.h"
+
+namespace hm {
+
+struct ProfRec {
+  const char *name;
+  hipEvent_t a, b;
+};
+
+static std::mutex g_mu;
+static bool g_on = false;
+static std::vector<ProfRec> g_open;  // recorded, not yet harvested
+struct ProfTot {
+  std::string name;
+  int64_t count;
+  double ms;
+};
+static std::vector<ProfTot> g_tot;
+
+bool prof_on() { return g_on; }
+
+void *prof_begin(const char *name, hipStream_t st) {
+  if (!g_on) return nullptr;
+  ProfRec *r = new ProfRec{name, nullptr, nullptr};
+  if (hipEventCreate(&r->a) != hipSuccess || hipEventCreate(&r->b) != hipSuccess) {
+    delete r;
+    return nullptr;
+  }
+  hipEventRecord(r->a, st);
+  return r;
+}
+
+void prof_end(void *tok, hipStream_t st) {
+  if (!tok) return;
+  ProfRec *r = (ProfRec *)tok;
+  hipEventRecord(r->b, st);
+  std::lock_guard<std::mutex> g(g_mu);
+  g_open.push_back(*r);
+  delete r;
+}
+
+static void harvest() {
+  for (auto &r : g_open) {
+    float ms = 0.f;
+    hipEventSynchronize(r.b);
+    hipEventElapsedTime(&ms, r.a, r.b);
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+    bool found = false;
+    for (auto &t : g_tot)
+      if (t.name == r.name) {
+        t.count++;
+        t.ms += ms;
+        found = true;
+        break;
+      }
+    if (!found) g_tot.push_back(ProfTot{r.name, 1, (double)ms});
+  }
+  g_open.clear();
+}
+
+}  // namespace hm
+
+extern "C" {
+
+hm_status hm_profile_enable(int on) {
+  std::lock_guard<std::mutex> g(hm::g_mu);
+  hm::g_on = on != 0;
+  return HM_OK;
+}
+
+hm_status hm_profile_reset(void) {
+  std::lock_guard<std::mutex> g(hm::g_mu);
+  hm::harvest();
+  hm::g_tot.clear();
+  return HM_OK;
+}
+
+hm_status hm_profile_query(int index, char *name, size_t name_len, int64_t *count, double *ms) {
+  std::lock_guard<std::mutex> g(hm::g_mu);
+  hm::harvest();
+  if (index < 0 || index >= (int)hm::g_tot.size()) return (hm_status)hm::fail(hm::E_ARG, "profile index %d out of range", index);
+  const auto &t = hm::g_tot[index];
+  if (name && name_len) {
+    strncpy(name, t.name.c_str(), name_len - 1);
+    name[name_len - 1] = 0;
+  }
+  if (count) *count = t.count;
+  if (ms) *ms = t.ms;
+  return HM_OK;
+}
+
+}  // extern "C"

@@ -49,8 +49,8 @@ __host__ __device__ constexpr int rp_H(int NL, int RB, int k) { return RB < NL -
 template <typename T>
 __device__ __forceinline__ void cmul_conj(vec2<T> y, vec2<T> x, T &re, T &im) {
   // conj(y) * x
-  re = __builtin_fma(y.x, x.x, y.y * x.y);
-  im = __builtin_fma(y.x, x.y, -(y.y * x.x));
+  re = fmaT(y.x, x.x, y.y * x.y);
+  im = fmaT(y.x, x.y, -(y.y * x.x));
 }
 
 template <typename T, int NT, int RB, int NL, bool WRITE, int QM>
@@ -74,7 +74,7 @@ __global__ __launch_bounds__(NT) void k_sre_rowpass(RowPassArgs A) {
   const uint32_t tau = threadIdx.x;
   const uint32_t tlo = tau & (SEG - 1);
   const uint32_t g = tau >> S0;
-  const uint64_t half = 1ull << A.nf;
+  const uint32_t half = 1u << A.nf;
 
   for (int64_t tile = blockIdx.x; tile < A.n_tiles; tile += gridDim.x) {
     const int64_t rt = tile * G + g;
@@ -102,13 +102,14 @@ __global__ __launch_bounds__(NT) void k_sre_rowpass(RowPassArgs A) {
       for (int r = 0; r < R; ++r) re[r] = im[r] = T(0);
     } else if (a == 0) {
       // a = 0: fold on the top qubit; u_c = (r0 + r1) + i (r0 - r1).
-      const uint64_t cb = (ch << NL) | tlo;
+      const uint32_t cb = ((uint32_t)ch << NL) | tlo;
+      const vec2<T> *p1b = psi + half;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const uint64_t c = cb + ((uint64_t)r << S0);
-        const vec2<T> p0 = psi[c], p1 = psi[c + half];
-        const T r0 = __builtin_fma(p0.x, p0.x, p0.y * p0.y);
-        const T r1 = __builtin_fma(p1.x, p1.x, p1.y * p1.y);
+        const uint32_t c = cb + ((uint32_t)r << S0);
+        const vec2<T> p0 = ld32(psi, c), p1 = ld32(p1b, c);
+        const T r0 = fmaT(p0.x, p0.x, p0.y * p0.y);
+        const T r1 = fmaT(p1.x, p1.x, p1.y * p1.y);
         re[r] = r0 + r1;
         im[r] = r0 - r1;
       }
@@ -116,42 +117,43 @@ __global__ __launch_bounds__(NT) void k_sre_rowpass(RowPassArgs A) {
       const int j = 63 - __builtin_clzll(a);
       if (j >= NL) {
         // fold bit inside the row index: columns are untouched, rows map c_h -> insert0(c_h, j - NL)
-        const uint64_t xr = ins0(ch, j - NL);
-        const uint64_t yr = xr ^ (a >> NL);
+        const uint32_t xr = ins0_32((uint32_t)ch, j - NL);
+        const uint32_t yr = xr ^ (uint32_t)(a >> NL);
         const uint32_t alo = (uint32_t)a & (SEG - 1);
         const uint32_t amid = ((uint32_t)(a >> S0)) & (R - 1);
-        const uint64_t xb = (xr << NL) | tlo;
-        const uint64_t yb = (yr << NL) | (tlo ^ alo);
+        const uint32_t xb = (xr << NL) | tlo;
+        const uint32_t yb = (yr << NL) | (tlo ^ alo);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          const vec2<T> px = psi[xb + ((uint64_t)r << S0)];
-          const vec2<T> py = psi[yb + ((uint64_t)(r ^ amid) << S0)];
+          const vec2<T> px = ld32(psi, xb + ((uint32_t)r << S0));
+          const vec2<T> py = ld32(psi, yb + ((uint32_t)(r ^ amid) << S0));
           cmul_conj<T>(py, px, re[r], im[r]);
         }
       } else if (j >= S0) {
         // fold bit among the register bits of the first round
-        const uint64_t base = ch << (NL + 1);
+        const uint32_t base = (uint32_t)ch << (NL + 1);
         const int jj = j - S0;
         const uint32_t alo = (uint32_t)a & (SEG - 1);
         const uint32_t ahi = (uint32_t)(a >> S0);
-        const uint64_t xb = base | tlo;
-        const uint64_t yb = base | (tlo ^ alo);
+        const uint32_t xb = base | tlo;
+        const uint32_t yb = base | (tlo ^ alo);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           const uint32_t e = ins0_32((uint32_t)r, jj);
-          const vec2<T> px = psi[xb + ((uint64_t)e << S0)];
-          const vec2<T> py = psi[yb + ((uint64_t)(e ^ ahi) << S0)];
+          const vec2<T> px = ld32(psi, xb + (e << S0));
+          const vec2<T> py = ld32(psi, yb + ((e ^ ahi) << S0));
           cmul_conj<T>(py, px, re[r], im[r]);
         }
       } else {
         // small shifts (a < 2^S0): generic index arithmetic
-        const uint64_t base = ch << (NL + 1);
+        const uint32_t base = (uint32_t)ch << (NL + 1);
+        const uint32_t a32 = (uint32_t)a;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          const uint64_t c = (uint64_t)tlo | ((uint64_t)r << S0);
-          const uint64_t x = base | ins0(c, j);
-          const vec2<T> px = psi[x];
-          const vec2<T> py = psi[x ^ a];
+          const uint32_t c = tlo | ((uint32_t)r << S0);
+          const uint32_t x = base | ins0_32(c, j);
+          const vec2<T> px = ld32(psi, x);
+          const vec2<T> py = ld32(psi, x ^ a32);
           cmul_conj<T>(py, px, re[r], im[r]);
         }
       }
@@ -178,13 +180,13 @@ __global__ __launch_bounds__(NT) void k_sre_rowpass(RowPassArgs A) {
       // column to stay a column), so consecutive lanes write consecutive addresses.
       if (active) {
         vec2<T> *ex = (vec2<T> *)A.exch;
-        const uint64_t ob = ((uint64_t)rt << NL) | tlo;
+        const uint32_t ob = ((uint32_t)rt << NL) | tlo;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           vec2<T> v;
           v.x = re[r];
           v.y = im[r];
-          ex[ob + ((uint64_t)r << S0)] = v;
+          st32(ex, ob + ((uint32_t)r << S0), v);
         }
       }
     } else {
@@ -219,7 +221,28 @@ struct ColPassArgs {
   int nacc;
   int64_t n_tiles;
   QArgs qa;
+  // per-shift reduction of the previous batch's partials (written by the previous launch)
+  const double *prev_partials;
+  int64_t prev_n_slots;
+  uint64_t prev_a0;
+  const uint64_t *prev_rows;
+  double *prev_shift_sums;
+  int nf;
 };
+
+// Per-shift sum over column blocks (fixed order), unfolded and scaled.
+__device__ __forceinline__ void reduce_shift(const double *partials, int64_t slot, int64_t n_cb, int nacc, uint64_t a0,
+                                             const uint64_t *rows, int nf, const QArgs &qa, double *shift_sums) {
+  double s[HM_MAX_Q + 1];
+  for (int k = 0; k < nacc; ++k) s[k] = 0.0;
+  const double *p = partials + slot * n_cb * nacc;
+  for (int64_t c = 0; c < n_cb; ++c)
+    for (int k = 0; k < nacc; ++k) s[k] += p[c * nacc + k];
+  const uint64_t a = rows ? rows[slot] : a0 + (uint64_t)slot;
+  const bool bad = (a >> (nf + 1)) != 0;
+  unfold_scale(s, nacc, qa, a == 0);
+  for (int k = 0; k < nacc; ++k) shift_sums[slot * nacc + k] = bad ? __builtin_nan("") : s[k];
+}
 
 __host__ __device__ constexpr int cp_S(int NH, int RB, int CB, int k) {
   return CB + (RB * k < NH - RB ? RB * k : NH - RB);
@@ -247,16 +270,19 @@ __global__ __launch_bounds__(NT) void k_sre_colpass(ColPassArgs A) {
   const uint32_t col = tau & ((1u << CB) - 1u);
   const uint32_t rowhi = tau >> CB;
 
+  for (int64_t s = (int64_t)blockIdx.x * NT + tau; s < A.prev_n_slots; s += (int64_t)gridDim.x * NT)
+    reduce_shift(A.prev_partials, s, A.n_cb, A.nacc, A.prev_a0, A.prev_rows, A.nf, A.qa, A.prev_shift_sums);
+
   for (int64_t tile = blockIdx.x; tile < A.n_tiles; tile += gridDim.x) {
     const int64_t slot = tile / A.n_cb;
     const int64_t cb = tile - slot * A.n_cb;
     T re[R], im[R];
     {
-      const uint64_t base = ((uint64_t)slot << (NH + A.nl)) + ((uint64_t)cb << CB) + col;
+      const uint32_t base = ((uint32_t)slot << (NH + A.nl)) + ((uint32_t)cb << CB) + col;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const uint64_t row = (uint64_t)r | ((uint64_t)rowhi << RB);
-        const vec2<T> v = ex[base + (row << A.nl)];
+        const uint32_t row = (uint32_t)r | (rowhi << RB);
+        const vec2<T> v = ld32(ex, base + (row << A.nl));
         re[r] = v.x;
         im[r] = v.y;
       }
@@ -291,20 +317,11 @@ __global__ __launch_bounds__(NT) void k_sre_colpass(ColPassArgs A) {
   }
 }
 
-// per-shift sums from column-pass partials (fixed order over column blocks), unfolded and scaled
+// per-shift sums from column-pass partials of the last batch
 __global__ void k_sre_shift_reduce(const double *partials, int64_t n_slots, int64_t n_cb, int nacc, uint64_t a0,
                                    const uint64_t *rows, int nf, QArgs qa, double *shift_sums) {
   const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (slot >= n_slots) return;
-  double s[HM_MAX_Q + 1];
-  for (int k = 0; k < nacc; ++k) s[k] = 0.0;
-  const double *p = partials + slot * n_cb * nacc;
-  for (int64_t c = 0; c < n_cb; ++c)
-    for (int k = 0; k < nacc; ++k) s[k] += p[c * nacc + k];
-  const uint64_t a = rows ? rows[slot] : a0 + (uint64_t)slot;
-  const bool bad = (a >> (nf + 1)) != 0;
-  unfold_scale(s, nacc, qa, a == 0);
-  for (int k = 0; k < nacc; ++k) shift_sums[slot * nacc + k] = bad ? __builtin_nan("") : s[k];
+  if (slot < n_slots) reduce_shift(partials, slot, n_cb, nacc, a0, rows, nf, qa, shift_sums);
 }
 
 // Fixed-order sum over all per-shift sums; optionally finalise (Eq. sre).
@@ -358,6 +375,7 @@ static int64_t grid_for(int64_t tiles) { return tiles < 65536 ? tiles : 65536; }
 template <typename T, int NT, int RB, int NL, bool WRITE>
 static void launch_row_q(const RowPassArgs &A, bool q2, hipStream_t st) {
   const dim3 grid((unsigned)grid_for(A.n_tiles)), block(NT);
+  ProfScope prof(WRITE ? "sre_rowpass_write" : "sre_rowpass_resident", st);
   if (WRITE || !q2) hipLaunchKernelGGL((k_sre_rowpass<T, NT, RB, NL, WRITE, 0>), grid, block, 0, st, A);
   else hipLaunchKernelGGL((k_sre_rowpass<T, NT, RB, NL, WRITE, 2>), grid, block, 0, st, A);
 }
@@ -417,6 +435,7 @@ static void launch_col_nh(ColPassArgs A, bool q2, hipStream_t st) {
   A.n_cb = (int64_t)1 << (A.nl - CB);
   A.n_tiles = A.n_slots * A.n_cb;
   const dim3 grid((unsigned)grid_for(A.n_tiles)), block(NT);
+  ProfScope prof("sre_colpass", st);
   if (q2) hipLaunchKernelGGL((k_sre_colpass<T, NT, RB, NH, CB, 2>), grid, block, 0, st, A);
   else hipLaunchKernelGGL((k_sre_colpass<T, NT, RB, NH, CB, 0>), grid, block, 0, st, A);
 }
@@ -484,8 +503,11 @@ int sre_plan(int N, int dbl, int force_path, int64_t batch_opt, SrePlan *p) {
     P.nl = nl;
     P.nh = nh;
     P.col_tb = col_tb;
+    // The exchange of one batch (batch x 2^nf values) is sized to stay resident in the 256 MiB
+    // memory-side cache (MALL) while giving each launch enough tiles to fill the 256 CUs.
     const size_t per_shift = ((size_t)1 << P.nf) * (dbl ? 16 : 8);
-    int64_t b = batch_opt > 0 ? batch_opt : (int64_t)((64ull << 20) / per_shift);
+    int64_t b = batch_opt > 0 ? batch_opt : (int64_t)((128ull << 20) / per_shift);
+    if ((size_t)b * per_shift > (3ull << 30)) b = (int64_t)((3ull << 30) / per_shift);  // 32-bit offsets
     if (b < 1) b = 1;
     if (b > ((int64_t)1 << N)) b = (int64_t)1 << N;
     P.batch = (int)b;
@@ -505,7 +527,7 @@ size_t sre_workspace(const SrePlan &p, int nq, int64_t n_internal_slots) {
   size_t b = align256((size_t)n_internal_slots * nacc * sizeof(double));
   if (p.path == 2) {
     b += exch_bytes(p);
-    b += align256((size_t)p.batch * (size_t)col_blocks(p) * nacc * sizeof(double));
+    b += 2 * align256((size_t)p.batch * (size_t)col_blocks(p) * nacc * sizeof(double));  // double-buffered
   }
   return b < 256 ? 256 : b;
 }
@@ -531,10 +553,15 @@ static int shift_sums_t(const SrePlan &p, const void *psi, const QArgs &qa, uint
     if (e) return e;
     return hipPeekAtLastError() == hipSuccess ? OK : fail(E_HIP, "SRE row pass launch: %s", hipGetErrorString(hipGetLastError()));
   }
+  // Two-pass: per batch, row pass (writes the exchange) then column pass (reads it, writes per
+  // column-block partials and reduces the previous batch's partials to per-shift sums).
   const int64_t n_cb = col_blocks(p);
   void *exch = w;
-  double *partials = (double *)(w + exch_bytes(p));
-  for (int64_t s0 = 0; s0 < n_slots; s0 += p.batch) {
+  const size_t pbytes = align256((size_t)p.batch * (size_t)n_cb * nacc * sizeof(double));
+  double *partials[2] = {(double *)(w + exch_bytes(p)), (double *)(w + exch_bytes(p) + pbytes)};
+  int64_t prev_s0 = 0, prev_nb = 0;
+  int k = 0;
+  for (int64_t s0 = 0; s0 < n_slots; s0 += p.batch, ++k) {
     const int64_t nb = (n_slots - s0) < p.batch ? (n_slots - s0) : p.batch;
     RowPassArgs A{};
     A.psi = psi;
@@ -552,14 +579,26 @@ static int shift_sums_t(const SrePlan &p, const void *psi, const QArgs &qa, uint
     C.exch = exch;
     C.nl = p.nl;
     C.n_slots = nb;
-    C.partials = partials;
+    C.partials = partials[k & 1];
     C.nacc = nacc;
     C.qa = qa;
+    C.nf = p.nf;
+    C.prev_partials = partials[(k + 1) & 1];
+    C.prev_n_slots = prev_nb;
+    C.prev_a0 = a0 + (uint64_t)prev_s0;
+    C.prev_rows = rows ? rows + prev_s0 : nullptr;
+    C.prev_shift_sums = shift_sums + prev_s0 * nacc;
     e = launch_colpass<T>(p.col_tb, p.nh, C, q2, st);
     if (e) return e;
+    prev_s0 = s0;
+    prev_nb = nb;
+  }
+  {
     const int thr = 128;
-    hipLaunchKernelGGL(k_sre_shift_reduce, dim3((unsigned)((nb + thr - 1) / thr)), dim3(thr), 0, st, partials, nb,
-                       n_cb, nacc, a0 + (uint64_t)s0, rows ? rows + s0 : nullptr, p.nf, qa, shift_sums + s0 * nacc);
+    ProfScope prof("sre_shift_reduce", st);
+    hipLaunchKernelGGL(k_sre_shift_reduce, dim3((unsigned)((prev_nb + thr - 1) / thr)), dim3(thr), 0, st,
+                       partials[(k + 1) & 1], prev_nb, n_cb, nacc, a0 + (uint64_t)prev_s0,
+                       rows ? rows + prev_s0 : nullptr, p.nf, qa, shift_sums + prev_s0 * nacc);
   }
   return hipPeekAtLastError() == hipSuccess ? OK : fail(E_HIP, "SRE two-pass launch: %s", hipGetErrorString(hipGetLastError()));
 }
@@ -581,6 +620,7 @@ int sre_run(const SrePlan &p, const void *psi, const QArgs &qa, uint64_t a0, con
 
 int sre_reduce_shifts(const double *shift_sums, int64_t n_slots, const QArgs &qa, int N, double *sums, double *out,
                       hipStream_t st) {
+  ProfScope prof("sre_total", st);
   hipLaunchKernelGGL(k_sre_total, dim3(1), dim3(256), 0, st, shift_sums, n_slots, nacc_of(qa), qa, N, sums, out);
   return hipPeekAtLastError() == hipSuccess ? OK : fail(E_HIP, "SRE reduce launch: %s", hipGetErrorString(hipGetLastError()));
 }

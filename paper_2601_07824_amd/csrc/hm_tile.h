@@ -23,6 +23,21 @@ template <typename T> using vec2 = typename vec2_of<T>::type;
 
 __host__ __device__ constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x >> 1); }
 
+// Fused multiply-add in the precision of T (the plain builtin would promote floats to double).
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// Load / store element idx of an array given by a uniform base pointer and a 32-bit element index
+// (the byte offset stays in one 32-bit register; every buffer here is smaller than 4 GiB).
+template <typename V>
+__device__ __forceinline__ V ld32(const V *base, uint32_t idx) {
+  return *reinterpret_cast<const V *>(reinterpret_cast<const char *>(base) + (uint32_t)(idx * (uint32_t)sizeof(V)));
+}
+template <typename V>
+__device__ __forceinline__ void st32(V *base, uint32_t idx, V v) {
+  *reinterpret_cast<V *>(reinterpret_cast<char *>(base) + (uint32_t)(idx * (uint32_t)sizeof(V))) = v;
+}
+
 template <int S, int RB>
 __device__ __forceinline__ uint32_t lay(uint32_t tau, uint32_t rho) {
   return (tau & ((1u << S) - 1u)) | (rho << S) | ((tau >> S) << (S + RB));
@@ -124,7 +139,7 @@ template <typename T, int QM> struct Acc {
     const T t = x * x;
     a[0] += t;
     if constexpr (QM == 2) {
-      a[1] = __builtin_fma(t, t, a[1]);
+      a[1] = fmaT(t, t, a[1]);
     } else {
 #pragma unroll
       for (int i = 0; i < HM_MAX_Q; ++i) {
