@@ -78,22 +78,27 @@ __device__ __forceinline__ void wht_regs(T (&re)[R], T (&im)[R]) {
 }
 
 // Move the tile from layout SA to layout SB through LDS (all NT threads must call it).
+// Threads with act == false (padding threads of a block larger than the tile) skip the LDS traffic.
 template <typename T, int R, int RB, int SA, int SB>
-__device__ __forceinline__ void relayout(T (&re)[R], T (&im)[R], vec2<T> *lds, uint32_t tau) {
+__device__ __forceinline__ void relayout(T (&re)[R], T (&im)[R], vec2<T> *lds, uint32_t tau, bool act = true) {
   __syncthreads();  // earlier readers of lds are done
+  if (act) {
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    vec2<T> v;
-    v.x = re[r];
-    v.y = im[r];
-    lds[ldspad<RB>(lay<SA, RB>(tau, (uint32_t)r))] = v;
+    for (int r = 0; r < R; ++r) {
+      vec2<T> v;
+      v.x = re[r];
+      v.y = im[r];
+      lds[ldspad<RB>(lay<SA, RB>(tau, (uint32_t)r))] = v;
+    }
   }
   __syncthreads();
+  if (act) {
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    vec2<T> v = lds[ldspad<RB>(lay<SB, RB>(tau, (uint32_t)r))];
-    re[r] = v.x;
-    im[r] = v.y;
+    for (int r = 0; r < R; ++r) {
+      vec2<T> v = lds[ldspad<RB>(lay<SB, RB>(tau, (uint32_t)r))];
+      re[r] = v.x;
+      im[r] = v.y;
+    }
   }
 }
 

@@ -1,0 +1,133 @@
+"""GPU parity of the fused forward + adjoint SRE kernel (dM_q/dpsi) against the FP64 oracle gradients,
+central finite differences and the homogeneity / phase-invariance identities, through the C-ABI and
+through torch.autograd (including a parameterised RY/RZ + CZ circuit).
+
+Tolerances: complex128 relative L2 <= 1e-9; complex64 (FP32 transforms, FP32 accumulation of the
+per-workgroup gradient partials, FP64 across workgroups) relative L2 <= 1e-4.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from synth import states as S
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def hm():
+    import paper_2601_07824_amd as m
+    m.lib()
+    return m
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def gpu_state(psi, c64):
+    if c64:
+        v, w = S.to_c64_exact(psi)
+        return torch.from_numpy(v).to(_dev()), w
+    return torch.from_numpy(psi).to(_dev()), psi
+
+
+@pytest.mark.parametrize("c64", [False, True])
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 7, 8, 10])
+def test_grad_vs_direct_oracle(orc, hm, n, c64):
+    psi = S.gaussian_state(n, seed=6000 + n)
+    x, w = gpu_state(psi, c64)
+    for q in (2.0, 3.0):
+        say(f"[grad] n={n} c64={c64} q={q}")
+        out, g = hm.sre_grad(x, q)
+        want_out, want_g = (orc.sre_grad_direct(w, q) if n <= 7 else orc.sre_grad_fwht(w, q))
+        got_g = g.cpu().numpy().astype(np.complex128)
+        tol = 1e-4 if c64 else 1e-9
+        assert rel_l2(got_g, want_g) < tol, (n, q, rel_l2(got_g, want_g))
+        np.testing.assert_allclose(out.cpu().numpy(), want_out, rtol=(1e-5 if c64 else 1e-11), atol=1e-6 if c64 else 1e-12)
+
+
+@pytest.mark.parametrize("c64,n", [(False, 11), (False, 12), (True, 12), (True, 13)])
+def test_grad_largest_resident_vs_fwht_oracle(orc, hm, n, c64):
+    psi = S.ry_rz_cz_state(n, np.random.default_rng(6100 + n).uniform(0, 2 * math.pi, (2, 2, n)))
+    x, w = gpu_state(psi, c64)
+    say(f"[grad resident max] n={n} c64={c64}")
+    out, g = hm.sre_grad(x, 2.0)
+    want_out, want_g = orc.sre_grad_fwht(w, 2.0)
+    assert rel_l2(g.cpu().numpy().astype(np.complex128), want_g) < (1e-4 if c64 else 1e-9)
+
+
+def test_grad_central_differences(hm):
+    """h = 1e-6 central differences of the FP64 GPU forward on sampled coordinates (Re and Im)."""
+    n = 9
+    psi = S.gaussian_state(n, seed=6200)
+    x = torch.from_numpy(psi).to(_dev())
+    _, g = hm.sre_grad(x, 2.0)
+    g = g.cpu().numpy()
+    h = 1e-6
+    for y in np.random.default_rng(6201).choice(2 ** n, 16, replace=False):
+        for unit in (1.0, 1j):
+            e = np.zeros_like(psi)
+            e[y] = unit * h
+            say(f"[grad fd] y={y} unit={unit}")
+            mp = hm.sre(torch.from_numpy(psi + e).to(_dev()), (2.0,))[0].item()
+            mm = hm.sre(torch.from_numpy(psi - e).to(_dev()), (2.0,))[0].item()
+            fd = (mp - mm) / (2 * h)
+            an = g[y].real if unit == 1.0 else g[y].imag
+            assert abs(fd - an) < 1e-6 * max(1.0, abs(an)), (y, unit, fd, an)
+
+
+@pytest.mark.parametrize("c64", [False, True])
+def test_homogeneity_and_phase_invariance(hm, c64):
+    n = 12
+    x, _ = gpu_state(S.gaussian_state(n, seed=6300), c64)
+    say(f"[grad identities] n={n} c64={c64}")
+    _, g = hm.sre_grad(x, 2.0)
+    ip = torch.vdot(g.to(torch.complex128), x.to(torch.complex128)).item()
+    want = 4 * 2.0 / ((1 - 2.0) * math.log(2))  # -8 / ln 2
+    tol = 1e-4 if c64 else 1e-9
+    assert abs(ip.real - want) < tol * abs(want) and abs(ip.imag) < tol * abs(want), ip
+
+
+def test_autograd_through_circuit(orc, hm):
+    """d M_2(psi(theta)) / d theta via torch.autograd + the library adjoint, vs FD on the angles."""
+    n = 8
+    dev = _dev()
+    ang0 = np.random.default_rng(6400).uniform(0, 2 * math.pi, (2, 2, n))
+    ang = torch.tensor(ang0, dtype=torch.float64, device=dev, requires_grad=True)
+    psi = S.ry_rz_cz_state_torch(n, ang)
+    say("[grad autograd] circuit n=8")
+    m2 = hm.SRE.apply(psi, 2.0)
+    m2.backward()
+    got = ang.grad.cpu().numpy()
+    h = 1e-6
+    fd = np.zeros_like(ang0)
+    for idx in np.ndindex(ang0.shape):
+        ap, am = ang0.copy(), ang0.copy()
+        ap[idx] += h
+        am[idx] -= h
+        fp = orc.sre_fwht(S.ry_rz_cz_state(n, ap), (2.0,))[0]
+        fm = orc.sre_fwht(S.ry_rz_cz_state(n, am), (2.0,))[0]
+        fd[idx] = (fp - fm) / (2 * h)
+    assert np.max(np.abs(got - fd)) < 1e-6 * max(1.0, np.max(np.abs(fd))), np.max(np.abs(got - fd))
+    assert abs(m2.item() - orc.sre_fwht(S.ry_rz_cz_state(n, ang0), (2.0,))[0]) < 1e-10
+
+
+def test_grad_determinism(hm):
+    x, _ = gpu_state(S.gaussian_state(11, seed=6500), True)
+    say("[grad determinism]")
+    a = hm.sre_grad(x, 2.0)[1].cpu().numpy()
+    b = hm.sre_grad(x, 2.0)[1].cpu().numpy()
+    assert np.array_equal(a, b)
