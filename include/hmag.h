@@ -67,12 +67,29 @@ const char *hm_last_error(void);
 /* Version string of this build. */
 const char *hm_version(void);
 
-/* Options (testing and tuning).  HM_OPT_FORCE_PATH selects the SRE kernel family:
- *   0 = automatic, 1 = workgroup-resident (one workgroup holds a whole folded shift vector),
- *   2 = two-pass (row pass, exchange through device memory, column pass).
- * A forced path outside its supported n range makes the SRE calls return HM_E_UNSUPPORTED.
- * HM_OPT_BATCH_SHIFTS sets how many X-shifts one two-pass launch pair covers (0 = automatic). */
-typedef enum { HM_OPT_FORCE_PATH = 1, HM_OPT_BATCH_SHIFTS = 2 } hm_option;
+/* Options (testing and tuning); 0 always means "automatic".
+ *   HM_OPT_FORCE_PATH: SRE kernel family, 1 = workgroup-resident (one workgroup holds a whole
+ *     folded shift vector), 2 = two-pass (row pass, exchange through device memory, column pass).
+ *   HM_OPT_BATCH_SHIFTS: X-shifts covered by one two-pass launch pair.
+ *   HM_OPT_ROW_RB / HM_OPT_COL_RB: log2 of the values each thread holds in registers in the
+ *     two-pass row / column kernels (4 or 5 for HM_C64, 4 for HM_C128).
+ *   HM_OPT_ROW_BITS: index bits handled by the two-pass row pass (6..13); the column pass takes
+ *     the remaining n - 1 - row_bits.
+ *   HM_OPT_PIPELINE: two-pass launches, 1 = one row pass then one column pass per batch of
+ *     shifts, 2 = pipelined (each launch runs the row pass of batch k beside the column pass of
+ *     batch k - 1, with two exchange buffers; default tiles and split only).
+ *   HM_OPT_LDS_SPLIT: pipelined kernels only, 1 = stage complex values through LDS, 2 = stage
+ *     real and imaginary parts one after the other (half the LDS per workgroup).
+ * A combination outside the built kernels makes the SRE calls return HM_E_UNSUPPORTED. */
+typedef enum {
+  HM_OPT_FORCE_PATH = 1,
+  HM_OPT_BATCH_SHIFTS = 2,
+  HM_OPT_ROW_RB = 3,
+  HM_OPT_COL_RB = 4,
+  HM_OPT_ROW_BITS = 5,
+  HM_OPT_PIPELINE = 6,
+  HM_OPT_LDS_SPLIT = 7
+} hm_option;
 hm_status hm_set_option(hm_handle h, hm_option opt, int64_t value);
 
 /* ------------------------------------------------------------------------------------------ */
@@ -83,7 +100,8 @@ typedef enum {
   HM_OP_SRE_ROWS = 1,   /* hm_sre_rows; count = n_rows                                       */
   HM_OP_ROW_VALUES = 2, /* hm_sre_row_values (count ignored)                                 */
   HM_OP_SRE_GRAD = 3,   /* hm_sre_grad (count ignored)                                       */
-  HM_OP_MANA = 4        /* hm_mana and hm_mana_partial (count ignored)                       */
+  HM_OP_MANA = 4,       /* hm_mana and hm_mana_partial (count ignored)                       */
+  HM_OP_SRE_SAMPLED = 5 /* hm_sre_sampled; count = n_rows                                    */
 } hm_op;
 hm_status hm_workspace_size(hm_handle h, hm_op op, int n, hm_dtype dtype, int n_q, int64_t count,
                             size_t *bytes);
@@ -92,7 +110,7 @@ hm_status hm_workspace_size(hm_handle h, hm_op op, int n, hm_dtype dtype, int n_
 /* Qubits: stabilizer Renyi entropy (Eq. sre, Algorithm 2)                                     */
 /* ------------------------------------------------------------------------------------------ */
 /* out[0..n_q-1] = M_{q_i}(psi); out[n_q] = lost_norm = 1 - sum_P <P>^2 / 2^n.
- * 1 <= n <= 26.  out: device, n_q + 1 doubles. */
+ * 1 <= n <= 26 (HM_C64) or 25 (HM_C128).  out: device, n_q + 1 doubles. */
 hm_status hm_sre(hm_handle h, const void *psi, int n, hm_dtype dtype, const double *q, int n_q,
                  double *out, void *ws, size_t ws_bytes, hipStream_t stream);
 
@@ -132,6 +150,32 @@ hm_status hm_sre_row_values(hm_handle h, const void *psi, int n, hm_dtype dtype,
 hm_status hm_sre_grad(hm_handle h, const void *psi, int n, hm_dtype dtype, double q, double *out,
                       void *grad, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* Many states, each of its own qubit count, in one call (all of one dtype and one q list).
+ * psis: HOST array of `batch` DEVICE pointers (one state each); ns: HOST array of their n.
+ * out: device, batch * (n_q + 1) doubles; out[s*(n_q+1) + i] = M_{q_i}(psi_s), out[s*(n_q+1) + n_q]
+ * = lost_norm of state s (as hm_sre).  States of equal n that fit the workgroup-resident kernels
+ * (n <= 16 for HM_C64, n <= 15 for HM_C128) are evaluated together, up to 64 per launch (the state
+ * pointers travel in the kernel arguments, no host-to-device copy); larger states run one after
+ * another through the two-pass kernels.  Workspace: hm_sre_batched_workspace. */
+hm_status hm_sre_batched_workspace(hm_handle h, const int *ns, int batch, hm_dtype dtype, int n_q,
+                                   size_t *bytes);
+hm_status hm_sre_batched(hm_handle h, const void *const *psis, const int *ns, int batch, hm_dtype dtype,
+                         const double *q, int n_q, double *out, void *ws, size_t ws_bytes,
+                         hipStream_t stream);
+
+/* Monte Carlo estimate of M_2 from sampled X-rows (Sec. on sampling the Pauli spectrum; a row is
+ * one transform, Eq. feP).  S(a) = sum_b |chi_b(a)|^4 and M_2 = -log2(mean over all a of S(a)).  The
+ * row a = 0 holds the identity, whose single term <I>^4 = 1 dominates the sum for typical states
+ * and would almost never be drawn, so that row is always evaluated exactly and the sampled rows
+ * (caller-drawn, e.g. i.i.d. uniform in [1, 2^n); entries equal to 0 are skipped) estimate the
+ * mean over a != 0:
+ *   S_hat = (S(0) + (2^n - 1) mean_k S(a_k)) / 2^n,  M2_hat = -log2 S_hat.
+ * out (device, 4 doubles) = {M2_hat, its standard error (2^n - 1) std_k S / (2^n sqrt(K) S_hat ln 2)
+ * with K the number of nonzero rows, S_hat, std_k S(a_k)}.  n_rows >= 2; K < 2 gives NaN errors.
+ * Workspace: hm_workspace_size(HM_OP_SRE_SAMPLED, count = n_rows). */
+hm_status hm_sre_sampled(hm_handle h, const void *psi, int n, hm_dtype dtype, const uint64_t *rows,
+                         int64_t n_rows, double *out, void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* ------------------------------------------------------------------------------------------ */
 /* Qutrits: pure-state mana (Eq. mana2, Algorithm 4)                                            */
 /* ------------------------------------------------------------------------------------------ */
@@ -150,9 +194,10 @@ hm_status hm_mana_partial(hm_handle h, const void *psi, int n, hm_dtype dtype, u
 /* ------------------------------------------------------------------------------------------ */
 /* Kernel timing (diagnostics)                                                                 */
 /* ------------------------------------------------------------------------------------------ */
-/* While enabled, each kernel launch is bracketed by hipEvents recorded on its stream.  Off by
- * default; process-wide. */
-hm_status hm_profile_enable(int on);
+/* every > 0: every every-th launch of each kernel family (the first, the every+1-th, ...) is
+ * bracketed by hipEvents recorded on its stream; 0 turns timing off (the default).  Sampling keeps
+ * the event overhead of long launch sequences small.  Process-wide. */
+hm_status hm_profile_enable(int every);
 /* Drops the accumulated timings. */
 hm_status hm_profile_reset(void);
 /* Timing of kernel family `index` (0-based, in order of first launch): its name (NUL-terminated,

@@ -18,7 +18,7 @@ from typing import Sequence
 
 __all__ = [
     "HmError", "lib", "lib_path", "Context", "default_context", "sre", "sre_partial", "sre_finalize",
-    "sre_rows", "sre_row_values", "sre_grad", "SRE", "mana", "mana_partial", "workspace_size",
+    "sre_rows", "sre_row_values", "sre_grad", "SRE", "sre_batched", "sre_sampled", "mana", "mana_partial", "workspace_size",
     "HM_C64", "HM_C128", "profile_enable", "profile_reset", "profile_read", "OP_SRE", "OP_SRE_ROWS", "OP_ROW_VALUES", "OP_SRE_GRAD", "OP_MANA",
     "EXPORTED_SYMBOLS",
 ]
@@ -27,8 +27,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 lib_path = os.path.join(_HERE, "libhmag.so")
 
 HM_C64, HM_C128 = 0, 1
-OP_SRE, OP_SRE_ROWS, OP_ROW_VALUES, OP_SRE_GRAD, OP_MANA = 0, 1, 2, 3, 4
-OPT_FORCE_PATH, OPT_BATCH_SHIFTS = 1, 2
+OP_SRE, OP_SRE_ROWS, OP_ROW_VALUES, OP_SRE_GRAD, OP_MANA, OP_SRE_SAMPLED = 0, 1, 2, 3, 4, 5
+OPT_FORCE_PATH, OPT_BATCH_SHIFTS, OPT_ROW_RB, OPT_COL_RB, OPT_ROW_BITS, OPT_PIPELINE, OPT_LDS_SPLIT = 1, 2, 3, 4, 5, 6, 7
 
 _vp = ctypes.c_void_p
 _i = ctypes.c_int
@@ -54,6 +54,9 @@ _SIGS = {
     "hm_sre_grad": (_i, [_vp, _vp, _i, _i, ctypes.c_double, _vp, _vp, _vp, _sz, _vp]),
     "hm_mana": (_i, [_vp, _vp, _i, _i, _vp, _vp, _sz, _vp]),
     "hm_mana_partial": (_i, [_vp, _vp, _i, _i, _u64, _u64, _vp, _vp, _sz, _vp]),
+    "hm_sre_batched_workspace": (_i, [_vp, ctypes.POINTER(_i), _i, _i, _i, ctypes.POINTER(_sz)]),
+    "hm_sre_batched": (_i, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_i), _i, _i, _dp, _i, _vp, _vp, _sz, _vp]),
+    "hm_sre_sampled": (_i, [_vp, _vp, _i, _i, _vp, _i64, _vp, _vp, _sz, _vp]),
     "hm_profile_enable": (_i, [_i]),
     "hm_profile_reset": (_i, []),
     "hm_profile_query": (_i, [_i, ctypes.c_char_p, _sz, ctypes.POINTER(_i64), _dp]),
@@ -191,9 +194,11 @@ def _workspace(nbytes: int, device):
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
 
 
-def profile_enable(on: bool = True):
-    """Bracket every library kernel launch with hipEvents on its stream (see hm_profile_enable)."""
-    _check(lib().hm_profile_enable(1 if on else 0))
+def profile_enable(on: bool | int = True):
+    """Bracket library kernel launches with hipEvents on their stream (see hm_profile_enable):
+    True = every launch, an int k > 1 = every k-th launch of each kernel family, False = off."""
+    every = int(on) if not isinstance(on, bool) else (1 if on else 0)
+    _check(lib().hm_profile_enable(every))
 
 
 def profile_reset():
@@ -270,6 +275,52 @@ def sre_rows(psi, rows, q=(2.0,), *, ctx: Context | None = None, stream=None):
     ws = _workspace(workspace_size(OP_SRE_ROWS, n, dt, nq, nr, ctx), psi.device)
     _check(lib().hm_sre_rows(ctx.h, _ptr(psi), n, dt, _ptr(rows), nr, qa, nq, _ptr(out), _ptr(ws), ws.numel(),
                              _stream(stream)))
+    return out
+
+
+def sre_batched(states, q=(2.0,), *, ctx: Context | None = None, stream=None):
+    """[M_q..., lost_norm] for each of several qubit states (list of GPU tensors of one dtype,
+    any lengths 2^n).  Returns a float64 tensor of shape (len(states), n_q + 1)."""
+    torch = _torch()
+    ctx = ctx or default_context()
+    sts, ns = [], []
+    for s in states:
+        s, n = _state(s, 2)
+        sts.append(s)
+        ns.append(n)
+    if not sts:
+        raise ValueError("no states")
+    dt = _dtype_code(sts[0])
+    if any(_dtype_code(s) != dt for s in sts):
+        raise TypeError("all states must share one dtype")
+    qa, nq = _q(q)
+    B = len(sts)
+    ns_c = (_i * B)(*ns)
+    ptrs = (_vp * B)(*[s.data_ptr() for s in sts])
+    b = _sz(0)
+    _check(lib().hm_sre_batched_workspace(ctx.h, ns_c, B, dt, nq, ctypes.byref(b)))
+    ws = _workspace(b.value, sts[0].device)
+    out = torch.empty((B, nq + 1), dtype=torch.float64, device=sts[0].device)
+    _check(lib().hm_sre_batched(ctx.h, ptrs, ns_c, B, dt, qa, nq, _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
+    out._hm_keepalive = (sts, ws)
+    return out
+
+
+def sre_sampled(psi, n_rows: int = 4096, seed: int = 0, rows=None, *, ctx: Context | None = None, stream=None):
+    """Monte Carlo M_2: tensor [M2_hat, standard error, S_hat, std S].  The a = 0 row is exact; the
+    other rows are drawn i.i.d. uniformly in [1, 2^n) with numpy's PCG64 (seed) unless given."""
+    import numpy as np
+    torch = _torch()
+    ctx = ctx or default_context()
+    psi, n = _state(psi, 2)
+    dt = _dtype_code(psi)
+    if rows is None:
+        rows = np.random.default_rng(seed).integers(1, 2 ** n, size=n_rows, dtype=np.uint64)
+    rows = torch.as_tensor(np.asarray(rows, dtype=np.int64)).to(psi.device)
+    out = torch.empty(4, dtype=torch.float64, device=psi.device)
+    ws = _workspace(workspace_size(OP_SRE_SAMPLED, n, dt, 1, rows.numel(), ctx), psi.device)
+    _check(lib().hm_sre_sampled(ctx.h, _ptr(psi), n, dt, _ptr(rows), rows.numel(), _ptr(out), _ptr(ws), ws.numel(),
+                                _stream(stream)))
     return out
 
 

@@ -7,6 +7,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <vector>
+
 #include "../../include/hmag.h"
 #include "hm_internal.h"
 #include "hm_tile.h"
@@ -14,8 +16,7 @@
 #define HM_VERSION_STRING "hmag 0.1.0 (gfx950)"
 
 struct hm_context {
-  int force_path = 0;
-  int64_t batch_shifts = 0;
+  hm::PlanOpts opts;
 };
 
 namespace hm {
@@ -122,11 +123,31 @@ hm_status hm_set_option(hm_handle h, hm_option opt, int64_t value) {
   switch (opt) {
     case HM_OPT_FORCE_PATH:
       if (value < 0 || value > 2) return (hm_status)fail(E_ARG, "HM_OPT_FORCE_PATH %lld not in {0,1,2}", (long long)value);
-      h->force_path = (int)value;
+      h->opts.force_path = (int)value;
       return HM_OK;
     case HM_OPT_BATCH_SHIFTS:
       if (value < 0 || value > (1ll << 30)) return (hm_status)fail(E_ARG, "HM_OPT_BATCH_SHIFTS %lld out of range", (long long)value);
-      h->batch_shifts = value;
+      h->opts.batch = value;
+      return HM_OK;
+    case HM_OPT_ROW_RB:
+      if (value != 0 && value != 4 && value != 5) return (hm_status)fail(E_ARG, "HM_OPT_ROW_RB %lld not in {0,4,5}", (long long)value);
+      h->opts.row_rb = (int)value;
+      return HM_OK;
+    case HM_OPT_COL_RB:
+      if (value != 0 && value != 4 && value != 5) return (hm_status)fail(E_ARG, "HM_OPT_COL_RB %lld not in {0,4,5}", (long long)value);
+      h->opts.col_rb = (int)value;
+      return HM_OK;
+    case HM_OPT_ROW_BITS:
+      if (value != 0 && (value < 6 || value > 13)) return (hm_status)fail(E_ARG, "HM_OPT_ROW_BITS %lld not in {0, 6..13}", (long long)value);
+      h->opts.row_bits = (int)value;
+      return HM_OK;
+    case HM_OPT_PIPELINE:
+      if (value < 0 || value > 2) return (hm_status)fail(E_ARG, "HM_OPT_PIPELINE %lld not in {0,1,2}", (long long)value);
+      h->opts.pipeline = (int)value;
+      return HM_OK;
+    case HM_OPT_LDS_SPLIT:
+      if (value < 0 || value > 2) return (hm_status)fail(E_ARG, "HM_OPT_LDS_SPLIT %lld not in {0,1,2}", (long long)value);
+      h->opts.lds_split = (int)value;
       return HM_OK;
   }
   return (hm_status)fail(E_ARG, "unknown option %d", (int)opt);
@@ -141,7 +162,7 @@ hm_status hm_workspace_size(hm_handle h, hm_op op, int n, hm_dtype dtype, int n_
     case HM_OP_SRE: {
       if (n_q < 1 || n_q > HM_MAX_Q) return (hm_status)fail(E_ARG, "n_q = %d outside [1, %d]", n_q, HM_MAX_Q);
       SrePlan p;
-      HM_TRY(sre_plan(n, dbl, h->force_path, h->batch_shifts, &p));
+      HM_TRY(sre_plan(n, dbl, h->opts, &p));
       *bytes = sre_workspace(p, n_q, (int64_t)1 << n);
       return HM_OK;
     }
@@ -149,7 +170,7 @@ hm_status hm_workspace_size(hm_handle h, hm_op op, int n, hm_dtype dtype, int n_
       if (n_q < 1 || n_q > HM_MAX_Q) return (hm_status)fail(E_ARG, "n_q = %d outside [1, %d]", n_q, HM_MAX_Q);
       if (count < 0) return (hm_status)fail(E_ARG, "count = %lld < 0", (long long)count);
       SrePlan p;
-      HM_TRY(sre_plan(n, dbl, h->force_path, h->batch_shifts, &p));
+      HM_TRY(sre_plan(n, dbl, h->opts, &p));
       *bytes = sre_workspace(p, n_q, 0);
       return HM_OK;
     }
@@ -161,6 +182,13 @@ hm_status hm_workspace_size(hm_handle h, hm_op op, int n, hm_dtype dtype, int n_
       if (n < 1 || n > 24) return (hm_status)fail(E_SIZE, "gradient: n = %d outside [1, 24]", n);
       *bytes = sre_grad_workspace(n, dbl);
       return HM_OK;
+    case HM_OP_SRE_SAMPLED: {
+      if (count < 2) return (hm_status)fail(E_ARG, "sampled: count = %lld < 2", (long long)count);
+      SrePlan p;
+      HM_TRY(sre_plan(n, dbl, h->opts, &p));
+      *bytes = align256((size_t)(count + 1) * 2 * sizeof(double)) + sre_workspace(p, 1, 0);
+      return HM_OK;
+    }
     case HM_OP_MANA: {
       if (n < 1 || n > 16) return (hm_status)fail(E_SIZE, "mana: n = %d outside [1, 16]", n);
       uint64_t D = 1;
@@ -182,7 +210,7 @@ hm_status hm_sre(hm_handle h, const void *psi, int n, hm_dtype dtype, const doub
   QArgs qa;
   HM_TRY(check_q(q, n_q, &qa));
   SrePlan p;
-  HM_TRY(sre_plan(n, dtype == HM_C128, h->force_path, h->batch_shifts, &p));
+  HM_TRY(sre_plan(n, dtype == HM_C128, h->opts, &p));
   const int64_t n_shifts = (int64_t)1 << n;
   HM_TRY(check_ws(ws, ws_bytes, sre_workspace(p, n_q, n_shifts)));
   return (hm_status)sre_run(p, psi, qa, 0, nullptr, n_shifts, nullptr, nullptr, out, ws, stream);
@@ -198,7 +226,7 @@ hm_status hm_sre_partial(hm_handle h, const void *psi, int n, hm_dtype dtype, co
   QArgs qa;
   HM_TRY(check_q(q, n_q, &qa));
   SrePlan p;
-  HM_TRY(sre_plan(n, dtype == HM_C128, h->force_path, h->batch_shifts, &p));
+  HM_TRY(sre_plan(n, dtype == HM_C128, h->opts, &p));
   const uint64_t D = 1ull << n;
   if (a0 > a1 || a1 > D) return (hm_status)fail(E_ARG, "shift range [%llu, %llu) not inside [0, 2^%d]", (unsigned long long)a0, (unsigned long long)a1, n);
   const int64_t n_slots = (int64_t)(a1 - a0);
@@ -227,7 +255,7 @@ hm_status hm_sre_rows(hm_handle h, const void *psi, int n, hm_dtype dtype, const
   QArgs qa;
   HM_TRY(check_q(q, n_q, &qa));
   SrePlan p;
-  HM_TRY(sre_plan(n, dtype == HM_C128, h->force_path, h->batch_shifts, &p));
+  HM_TRY(sre_plan(n, dtype == HM_C128, h->opts, &p));
   if (n_rows == 0) return HM_OK;
   HM_TRY(check_ptr(rows, 8, "rows"));
   HM_TRY(check_ptr(row_sums, 8, "row_sums"));
@@ -260,6 +288,103 @@ hm_status hm_sre_grad(hm_handle h, const void *psi, int n, hm_dtype dtype, doubl
   if (!(q > 0.0) || !isfinite(q) || q == 1.0) return (hm_status)fail(E_ARG, "gradient: q = %g must be positive, finite and != 1", q);
   HM_TRY(check_ws(ws, ws_bytes, sre_grad_workspace(n, dtype == HM_C128)));
   return (hm_status)sre_grad_launch(n, dtype == HM_C128, psi, q, out, grad, ws, ws_bytes, stream);
+}
+
+// Workspace of a batched call: the largest need over its size classes.
+static int batched_ws(hm_handle h, const int *ns, int batch, int dbl, int n_q, size_t *bytes) {
+  if (!ns || batch < 1) return fail(E_ARG, "batched: ns is NULL or batch = %d < 1", batch);
+  size_t need = 256;
+  for (int i = 0; i < batch; ++i) {
+    SrePlan p;
+    int st = sre_plan(ns[i], dbl, h->opts, &p);
+    if (st) return st;
+    size_t b;
+    if (p.path == 1) {
+      int cnt = 0;
+      for (int j = 0; j < batch; ++j) cnt += ns[j] == ns[i];
+      b = sre_states_workspace(p, n_q, cnt < HM_BATCH_PTRS ? cnt : HM_BATCH_PTRS);
+    } else {
+      b = sre_workspace(p, n_q, (int64_t)1 << ns[i]);
+    }
+    if (b > need) need = b;
+  }
+  *bytes = need;
+  return OK;
+}
+
+hm_status hm_sre_batched_workspace(hm_handle h, const int *ns, int batch, hm_dtype dtype, int n_q, size_t *bytes) {
+  g_err[0] = 0;
+  if (!h || !bytes) return (hm_status)fail(E_ARG, "h or bytes is NULL");
+  HM_TRY(check_dtype(dtype));
+  if (n_q < 1 || n_q > HM_MAX_Q) return (hm_status)fail(E_ARG, "n_q = %d outside [1, %d]", n_q, HM_MAX_Q);
+  return (hm_status)batched_ws(h, ns, batch, dtype == HM_C128, n_q, bytes);
+}
+
+hm_status hm_sre_batched(hm_handle h, const void *const *psis, const int *ns, int batch, hm_dtype dtype,
+                         const double *q, int n_q, double *out, void *ws, size_t ws_bytes, hipStream_t stream) {
+  g_err[0] = 0;
+  if (!h) return (hm_status)fail(E_ARG, "h is NULL");
+  HM_TRY(check_dtype(dtype));
+  if (!psis) return (hm_status)fail(E_ARG, "psis is NULL");
+  HM_TRY(check_ptr(out, 8, "out"));
+  QArgs qa;
+  HM_TRY(check_q(q, n_q, &qa));
+  const int dbl = dtype == HM_C128;
+  size_t need;
+  HM_TRY(batched_ws(h, ns, batch, dbl, n_q, &need));
+  for (int i = 0; i < batch; ++i) HM_TRY(check_ptr(psis[i], psi_align(dtype), "psis[i]"));
+  HM_TRY(check_ws(ws, ws_bytes, need));
+  // size classes in order of first appearance; resident classes go up to HM_BATCH_PTRS per launch
+  std::vector<char> done(batch, 0);
+  for (int i = 0; i < batch; ++i) {
+    if (done[i]) continue;
+    SrePlan p;
+    HM_TRY(sre_plan(ns[i], dbl, h->opts, &p));
+    if (p.path != 1) {
+      done[i] = 1;
+      HM_TRY(sre_run(p, psis[i], qa, 0, nullptr, (int64_t)1 << ns[i], nullptr, nullptr, out + (size_t)i * (n_q + 1), ws,
+                     stream));
+      continue;
+    }
+    std::vector<const void *> ptrs;
+    std::vector<double *> outs;
+    for (int j = i; j < batch; ++j) {
+      if (done[j] || ns[j] != ns[i]) continue;
+      done[j] = 1;
+      ptrs.push_back(psis[j]);
+      outs.push_back(out + (size_t)j * (n_q + 1));
+      if ((int)ptrs.size() == HM_BATCH_PTRS) {
+        HM_TRY(sre_run_states(p, ptrs.data(), (int)ptrs.size(), qa, outs.data(), ws, stream));
+        ptrs.clear();
+        outs.clear();
+      }
+    }
+    if (!ptrs.empty()) HM_TRY(sre_run_states(p, ptrs.data(), (int)ptrs.size(), qa, outs.data(), ws, stream));
+  }
+  return HM_OK;
+}
+
+hm_status hm_sre_sampled(hm_handle h, const void *psi, int n, hm_dtype dtype, const uint64_t *rows, int64_t n_rows,
+                         double *out, void *ws, size_t ws_bytes, hipStream_t stream) {
+  g_err[0] = 0;
+  if (!h) return (hm_status)fail(E_ARG, "h is NULL");
+  HM_TRY(check_dtype(dtype));
+  HM_TRY(check_ptr(psi, psi_align(dtype), "psi"));
+  HM_TRY(check_ptr(rows, 8, "rows"));
+  HM_TRY(check_ptr(out, 8, "out"));
+  if (n_rows < 2) return (hm_status)fail(E_ARG, "sampled: n_rows = %lld < 2", (long long)n_rows);
+  QArgs qa;
+  const double q2 = 2.0;
+  HM_TRY(check_q(&q2, 1, &qa));
+  SrePlan p;
+  HM_TRY(sre_plan(n, dtype == HM_C128, h->opts, &p));
+  const size_t rs_bytes = align256((size_t)(n_rows + 1) * 2 * sizeof(double));
+  HM_TRY(check_ws(ws, ws_bytes, rs_bytes + sre_workspace(p, 1, 0)));
+  double *rs = (double *)ws;
+  double *s0 = rs + 2 * n_rows;  // exact row a = 0
+  HM_TRY(sre_run(p, psi, qa, 0, nullptr, 1, s0, nullptr, nullptr, (char *)ws + rs_bytes, stream));
+  HM_TRY(sre_run(p, psi, qa, 0, rows, n_rows, rs, nullptr, nullptr, (char *)ws + rs_bytes, stream));
+  return (hm_status)sre_sampled_stats(rs, rows, n_rows, 2, s0, n, out, stream);
 }
 
 hm_status hm_mana(hm_handle h, const void *psi, int n, hm_dtype dtype, double *out, void *ws, size_t ws_bytes,

@@ -7,6 +7,8 @@
 #ifndef HM_MAX_Q
 #define HM_MAX_Q 8
 #endif
+// states per batched launch (their pointers travel in the kernel arguments)
+#define HM_BATCH_PTRS 64
 
 namespace hm {
 
@@ -40,10 +42,54 @@ struct SrePlan {
   int nl, nh;   // two-pass split: row bits, column-pass (row-index) bits; nl + nh = nf
   int batch;    // shifts per two-pass launch pair
   int col_tb;   // column tile bits (log2 of values per column tile)
+  int row_rb;   // register-tile bits of the two-pass row pass
+  int col_rb;   // register-tile bits of the column pass
+  int pipe;     // 1: row pass of batch k and column pass of batch k-1 share one launch
+  int split;    // 1: pipelined tiles stage one component at a time through LDS (half the LDS)
+};
+
+// Default two-pass split.  Column tiles hold 2^col_tb values; the row pass takes about half of the
+// folded bits, at least enough for one column tile's width, at least 6 and at most 13.
+constexpr int sre_default_col_tb(int nf, int dbl, int col_rb) {
+  return dbl ? (nf >= 12 ? 12 : 10) : (nf >= 13 ? 13 : 11);
+}
+constexpr int sre_default_nl(int nf, int col_tb, int col_rb) {
+  int nl = (nf + 1) / 2, nh = nf - nl;
+  if (nh < col_rb) { nh = col_rb; nl = nf - nh; }
+  if (nl < col_tb - nh) { nl = col_tb - nh; nh = nf - nl; }
+  if (nl < 6 && nf - 6 >= col_rb) nl = 6;  // shortest row the row-pass kernels are built for
+  if (nl > 13) nl = 13;
+  return nl;
+}
+// Folded-bit range with pipelined kernels built (default split and register tiles only).
+constexpr int SRE_PIPE_NF_MIN = 11, SRE_PIPE_NF_MAX = 25;
+inline bool sre_pipe_built(const SrePlan &p) {
+  const int rb = p.dbl ? 4 : 5;
+  return p.path == 2 && p.nf >= SRE_PIPE_NF_MIN && p.nf <= (p.dbl ? SRE_PIPE_NF_MAX - 1 : SRE_PIPE_NF_MAX) &&
+         p.row_rb == rb && p.col_rb == rb &&
+         p.col_tb == sre_default_col_tb(p.nf, p.dbl, rb) && p.nl == sre_default_nl(p.nf, p.col_tb, rb);
+}
+// Workspace pieces of the two-pass path: exchange buffer(s) and per-column-block partials.
+inline size_t sre_exch_bytes(const SrePlan &p) {
+  if (p.path != 2) return 0;
+  const size_t one = align256((size_t)p.batch * ((size_t)1 << p.nf) * (p.dbl ? 16 : 8));
+  return p.pipe ? 2 * one : one;
+}
+inline int64_t sre_col_blocks(const SrePlan &p) { return (int64_t)1 << (p.nl - (p.col_tb - p.nh)); }
+
+// Planner overrides (0 = automatic), set through hm_set_option.
+struct PlanOpts {
+  int force_path = 0;
+  int64_t batch = 0;
+  int row_rb = 0;
+  int col_rb = 0;
+  int row_bits = 0;
+  int pipeline = 0;  // 0 automatic, 1 off, 2 on
+  int lds_split = 0; // 0 automatic, 1 off, 2 on
 };
 
 // Fills a plan; returns OK or E_UNSUPPORTED/E_SIZE with a message.
-int sre_plan(int N, int dbl, int force_path, int64_t batch_opt, SrePlan *p);
+int sre_plan(int N, int dbl, const PlanOpts &o, SrePlan *p);
 // Workspace bytes for a forward run whose per-shift sums live in the workspace for
 // n_internal_slots shifts (0 when the caller supplies the per-shift output buffer).
 size_t sre_workspace(const SrePlan &p, int nq, int64_t n_internal_slots);
@@ -54,7 +100,27 @@ int sre_run(const SrePlan &p, const void *psi, const QArgs &qa, uint64_t a0, con
             double *ext_shift_sums, double *sums, double *out, void *ws, hipStream_t stream);
 int sre_reduce_shifts(const double *shift_sums, int64_t n_slots, const QArgs &qa, int N, double *sums, double *out,
                       hipStream_t stream);
+// Many states of one size n on the workgroup-resident path: per-shift sums of all shifts of the
+// n_states states (pointers psis) in one launch, then one fixed-order total per state into
+// outs[s][0..nq] = {M_q..., lost_norm}.
+int sre_run_states(const SrePlan &p, const void *const *psis, int n_states, const QArgs &qa, double *const *outs,
+                   void *ws, hipStream_t stream);
+size_t sre_states_workspace(const SrePlan &p, int nq, int n_states);
+// Monte Carlo M_2 from the row sums of sampled rows (rows equal to 0 skipped) and the exact row
+// sums of a = 0: out = {M2_hat, standard error, S_hat, std of the sampled S(a)}.
+int sre_sampled_stats(const double *row_sums, const uint64_t *rows, int64_t n_rows, int nacc, const double *s0_sums,
+                      int N, double *out, hipStream_t stream);
 int sre_finalize_launch(int N, const QArgs &qa, const double *sums, double *out, hipStream_t stream);
+
+// Per-dtype drivers of the SRE kernels (one translation unit each).
+int sre_shift_sums_f32(const SrePlan &p, const void *psi, const QArgs &qa, uint64_t a0, const uint64_t *rows,
+                       int64_t n_slots, double *shift_sums, char *w, hipStream_t st);
+int sre_shift_sums_f64(const SrePlan &p, const void *psi, const QArgs &qa, uint64_t a0, const uint64_t *rows,
+                       int64_t n_slots, double *shift_sums, char *w, hipStream_t st);
+int sre_pipe_f32(const SrePlan &p, const void *psi, const QArgs &qa, uint64_t a0, const uint64_t *rows,
+                 int64_t n_slots, double *shift_sums, char *w, hipStream_t st);
+int sre_pipe_f64(const SrePlan &p, const void *psi, const QArgs &qa, uint64_t a0, const uint64_t *rows,
+                 int64_t n_slots, double *shift_sums, char *w, hipStream_t st);
 
 // Row values <P_{a,b}> of one X-row (unfolded FWHT of one row).
 int sre_row_values_launch(int N, int dbl, const void *psi, uint64_t a, double *out, void *ws, hipStream_t stream);

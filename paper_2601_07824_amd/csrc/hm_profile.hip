@@ -1,9 +1,9 @@
 // hm_profile.hip -- optional per-kernel-family timing with HIP events on the launch stream.
 //
-// When enabled (hm_profile_enable(1)), every kernel launch of the library is bracketed by two
-// hipEventRecord calls on the stream it is enqueued on; hm_profile_query() synchronises on the
-// recorded events and reports, per kernel family, the number of launches and the summed
-// event-to-event device time.  Disabled by default; costs nothing when disabled.
+// When enabled (hm_profile_enable(k), k > 0), every k-th kernel launch of each kernel family is
+// bracketed by two hipEventRecord calls on the stream it is enqueued on; hm_profile_query()
+// synchronises on the recorded events and reports, per family, the number of timed launches and
+// their summed event-to-event device time.  Disabled by default; costs nothing when disabled.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
@@ -23,6 +23,12 @@ struct ProfRec {
 
 static std::mutex g_mu;
 static bool g_on = false;
+static int64_t g_every = 1;
+struct ProfSeen {
+  std::string name;
+  int64_t seen;
+};
+static std::vector<ProfSeen> g_seen;  // launches seen per family since the last reset
 static std::vector<ProfRec> g_open;  // recorded, not yet harvested
 struct ProfTot {
   std::string name;
@@ -35,19 +41,30 @@ bool prof_on() { return g_on; }
 
 void *prof_begin(const char *name, hipStream_t st) {
   if (!g_on) return nullptr;
+  {
+    std::lock_guard<std::mutex> g(g_mu);
+    ProfSeen *f = nullptr;
+    for (auto &s : g_seen)
+      if (s.name == name) f = &s;
+    if (!f) {
+      g_seen.push_back(ProfSeen{name, 0});
+      f = &g_seen.back();
+    }
+    if (f->seen++ % g_every != 0) return nullptr;
+  }
   ProfRec *r = new ProfRec{name, nullptr, nullptr};
   if (hipEventCreate(&r->a) != hipSuccess || hipEventCreate(&r->b) != hipSuccess) {
     delete r;
     return nullptr;
   }
-  hipEventRecord(r->a, st);
+  (void)hipEventRecord(r->a, st);
   return r;
 }
 
 void prof_end(void *tok, hipStream_t st) {
   if (!tok) return;
   ProfRec *r = (ProfRec *)tok;
-  hipEventRecord(r->b, st);
+  (void)hipEventRecord(r->b, st);
   std::lock_guard<std::mutex> g(g_mu);
   g_open.push_back(*r);
   delete r;
@@ -56,10 +73,10 @@ void prof_end(void *tok, hipStream_t st) {
 static void harvest() {
   for (auto &r : g_open) {
     float ms = 0.f;
-    hipEventSynchronize(r.b);
-    hipEventElapsedTime(&ms, r.a, r.b);
-    hipEventDestroy(r.a);
-    hipEventDestroy(r.b);
+    (void)hipEventSynchronize(r.b);
+    (void)hipEventElapsedTime(&ms, r.a, r.b);
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
     bool found = false;
     for (auto &t : g_tot)
       if (t.name == r.name) {
@@ -77,9 +94,11 @@ static void harvest() {
 
 extern "C" {
 
-hm_status hm_profile_enable(int on) {
+hm_status hm_profile_enable(int every) {
   std::lock_guard<std::mutex> g(hm::g_mu);
-  hm::g_on = on != 0;
+  if (every < 0) return (hm_status)hm::fail(hm::E_ARG, "profile sampling interval %d < 0", every);
+  hm::g_on = every > 0;
+  hm::g_every = every > 0 ? every : 1;
   return HM_OK;
 }
 
@@ -87,6 +106,7 @@ hm_status hm_profile_reset(void) {
   std::lock_guard<std::mutex> g(hm::g_mu);
   hm::harvest();
   hm::g_tot.clear();
+  hm::g_seen.clear();
   return HM_OK;
 }
 

@@ -20,7 +20,9 @@ __device__ __forceinline__ void cmul_conj(vec2<T> y, vec2<T> x, T &re, T &im) {
 
 // Product step of the row pass: for the thread's R values (row-task ch, thread part tlo, register
 // r at row position tlo + (r << S0)) form the folded vector u of shift a (see the file comment).
-template <typename T, int RB, int NL>
+// CH bounds how many registers' loads may be in flight: a scheduling fence after every CH values
+// keeps the compiler from hoisting all 2R gathers (register pressure decides occupancy).
+template <typename T, int RB, int NL, int CH = (1 << RB)>
 __device__ __forceinline__ void sre_product(const vec2<T> *__restrict__ psi, uint32_t half, uint64_t a, uint64_t ch,
                                             uint32_t tlo, bool active, T (&re)[1 << RB], T (&im)[1 << RB]) {
   constexpr int R = 1 << RB;
@@ -41,6 +43,9 @@ __device__ __forceinline__ void sre_product(const vec2<T> *__restrict__ psi, uin
       const T r1 = fmaT(p1.x, p1.x, p1.y * p1.y);
       re[r] = r0 + r1;
       im[r] = r0 - r1;
+      if constexpr (CH < R) {
+        if ((r + 1) % CH == 0) __builtin_amdgcn_sched_barrier(0);
+      }
     }
   } else {
     const int j = 63 - __builtin_clzll(a);
@@ -57,6 +62,9 @@ __device__ __forceinline__ void sre_product(const vec2<T> *__restrict__ psi, uin
         const vec2<T> px = ld32(psi, xb + ((uint32_t)r << S0));
         const vec2<T> py = ld32(psi, yb + ((uint32_t)(r ^ amid) << S0));
         cmul_conj<T>(py, px, re[r], im[r]);
+        if constexpr (CH < R) {
+          if ((r + 1) % CH == 0) __builtin_amdgcn_sched_barrier(0);
+        }
       }
     } else if (j >= S0) {
       // fold bit among the register bits of the first round
@@ -72,6 +80,9 @@ __device__ __forceinline__ void sre_product(const vec2<T> *__restrict__ psi, uin
         const vec2<T> px = ld32(psi, xb + (e << S0));
         const vec2<T> py = ld32(psi, yb + ((e ^ ahi) << S0));
         cmul_conj<T>(py, px, re[r], im[r]);
+        if constexpr (CH < R) {
+          if ((r + 1) % CH == 0) __builtin_amdgcn_sched_barrier(0);
+        }
       }
     } else {
       // small shifts (a < 2^S0): generic index arithmetic
@@ -84,6 +95,9 @@ __device__ __forceinline__ void sre_product(const vec2<T> *__restrict__ psi, uin
         const vec2<T> px = ld32(psi, x);
         const vec2<T> py = ld32(psi, x ^ a32);
         cmul_conj<T>(py, px, re[r], im[r]);
+        if constexpr (CH < R) {
+          if ((r + 1) % CH == 0) __builtin_amdgcn_sched_barrier(0);
+        }
       }
     }
   }

@@ -44,7 +44,17 @@ __device__ __forceinline__ uint32_t lay(uint32_t tau, uint32_t rho) {
 }
 
 template <int RB>
-__device__ __forceinline__ uint32_t ldspad(uint32_t idx) { return idx + (idx >> RB); }
+__host__ __device__ __forceinline__ constexpr uint32_t ldspad(uint32_t idx) { return idx + (idx >> RB); }
+
+// lay<S, RB>(tau, rho) split into its thread part and its register part.  The two occupy disjoint
+// bit fields, so lay = base + off and ldspad(lay) = ldspad(base) + ldspad(off): the register part
+// is a compile-time constant that folds into the immediate offset of the LDS instruction.
+template <int S, int RB>
+__device__ __forceinline__ uint32_t lay_base(uint32_t tau) {
+  return (tau & ((1u << S) - 1u)) | ((tau >> S) << (S + RB));
+}
+template <int S, int RB>
+__host__ __device__ __forceinline__ constexpr uint32_t lay_off(int rho) { return (uint32_t)rho << S; }
 
 // insert a zero bit at position j: bits >= j move up by one.
 __device__ __forceinline__ uint64_t ins0(uint64_t c, int j) {
@@ -81,6 +91,8 @@ __device__ __forceinline__ void wht_regs(T (&re)[R], T (&im)[R]) {
 // Threads with act == false (padding threads of a block larger than the tile) skip the LDS traffic.
 template <typename T, int R, int RB, int SA, int SB>
 __device__ __forceinline__ void relayout(T (&re)[R], T (&im)[R], vec2<T> *lds, uint32_t tau, bool act = true) {
+  const uint32_t ba = ldspad<RB>(lay_base<SA, RB>(tau));
+  const uint32_t bb = ldspad<RB>(lay_base<SB, RB>(tau));
   __syncthreads();  // earlier readers of lds are done
   if (act) {
 #pragma unroll
@@ -88,18 +100,39 @@ __device__ __forceinline__ void relayout(T (&re)[R], T (&im)[R], vec2<T> *lds, u
       vec2<T> v;
       v.x = re[r];
       v.y = im[r];
-      lds[ldspad<RB>(lay<SA, RB>(tau, (uint32_t)r))] = v;
+      lds[ba + ldspad<RB>(lay_off<SA, RB>(r))] = v;
     }
   }
   __syncthreads();
   if (act) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      vec2<T> v = lds[ldspad<RB>(lay<SB, RB>(tau, (uint32_t)r))];
+      vec2<T> v = lds[bb + ldspad<RB>(lay_off<SB, RB>(r))];
       re[r] = v.x;
       im[r] = v.y;
     }
   }
+}
+
+// Same as relayout, for tiles too large to stage both components at once: the real parts, then the
+// imaginary parts, go through a scalar LDS buffer of 2^TB (+ padding) values.
+// Same as relayout, for tiles too large to stage both components at once: the real parts, then the
+// imaginary parts, go through a scalar LDS buffer of 2^TB (+ padding) values.
+template <typename T, int R, int RB, int SA, int SB>
+__device__ __forceinline__ void relayout_one(T (&v)[R], T *lds, uint32_t tau) {
+  const uint32_t ba = ldspad<RB>(lay_base<SA, RB>(tau));
+  const uint32_t bb = ldspad<RB>(lay_base<SB, RB>(tau));
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < R; ++r) lds[ba + ldspad<RB>(lay_off<SA, RB>(r))] = v[r];
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[r] = lds[bb + ldspad<RB>(lay_off<SB, RB>(r))];
+}
+template <typename T, int R, int RB, int SA, int SB>
+__device__ __forceinline__ void relayout_split(T (&re)[R], T (&im)[R], T *lds, uint32_t tau) {
+  relayout_one<T, R, RB, SA, SB>(re, lds, tau);
+  relayout_one<T, R, RB, SA, SB>(im, lds, tau);
 }
 
 // Deterministic sum over aligned segments of SEG consecutive threads (SEG a power of two dividing

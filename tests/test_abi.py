@@ -88,6 +88,28 @@ def test_partial_rows_and_values_errors(L, h):
     assert L.hm_mana(h, good, 0, 0, good, ws, 1 << 30, None) == HM_E_SIZE
     assert L.hm_mana_partial(h, good, 4, 0, 0, 82, good, ws, 1 << 30, None) == HM_E_ARG
     assert L.hm_sre_finalize(8, q, 1, None, good, None) == HM_E_ARG
+    assert L.hm_sre_sampled(h, good, 8, 0, good, 1, good, ws, 1 << 30, None) == HM_E_ARG
+    assert L.hm_sre_sampled(h, good, 8, 0, None, 16, good, ws, 1 << 30, None) == HM_E_ARG
+    assert L.hm_sre_sampled(h, good, 8, 0, good, 16, good, ws, 64, None) == HM_E_WORKSPACE
+
+
+def test_batched_errors_and_workspace(L, h):
+    q = q_arr(2.0)
+    good, ws = P(0x100000), P(0x200000)
+    ns = (ctypes.c_int * 4)(3, 8, 8, 20)
+    ptrs = (P * 4)(good, good, good, good)
+    b, b1 = ctypes.c_size_t(), ctypes.c_size_t()
+    assert L.hm_sre_batched_workspace(h, ns, 4, 0, 1, ctypes.byref(b)) == HM_OK
+    assert L.hm_workspace_size(h, 0, 20, 0, 1, 0, ctypes.byref(b1)) == HM_OK
+    assert b.value >= b1.value and b.value % 256 == 0
+    assert L.hm_sre_batched_workspace(h, ns, 0, 0, 1, ctypes.byref(b)) == HM_E_ARG
+    bad = (ctypes.c_int * 2)(3, 27)
+    assert L.hm_sre_batched_workspace(h, bad, 2, 0, 1, ctypes.byref(b)) == HM_E_SIZE
+    assert L.hm_sre_batched(h, None, ns, 4, 0, q, 1, good, ws, 1 << 34, None) == HM_E_ARG
+    ptrs[2] = P(0x100004)
+    assert L.hm_sre_batched(h, ptrs, ns, 4, 0, q, 1, good, ws, 1 << 34, None) == HM_E_ALIGN
+    ptrs[2] = good
+    assert L.hm_sre_batched(h, ptrs, ns, 4, 0, q, 1, good, ws, 256, None) == HM_E_WORKSPACE
 
 
 def test_options_and_forced_paths(L, h):
@@ -100,9 +122,19 @@ def test_options_and_forced_paths(L, h):
         assert L.hm_set_option(hh, 1, 2) == HM_OK  # two-pass needs n >= 11 for c64
         assert L.hm_workspace_size(hh, 0, 8, 0, 1, 0, ctypes.byref(b)) == HM_E_UNSUPPORTED
         assert L.hm_workspace_size(hh, 0, 16, 0, 1, 0, ctypes.byref(b)) == HM_OK
-        assert L.hm_set_option(hh, 1, 1) == HM_OK  # workgroup-resident holds at most 2^13 folded c64 values
-        assert L.hm_workspace_size(hh, 0, 16, 0, 1, 0, ctypes.byref(b)) == HM_E_UNSUPPORTED
-        assert L.hm_workspace_size(hh, 0, 14, 0, 1, 0, ctypes.byref(b)) == HM_OK
+        assert L.hm_set_option(hh, 1, 1) == HM_OK  # workgroup-resident holds at most 2^15 folded c64 values
+        assert L.hm_workspace_size(hh, 0, 17, 0, 1, 0, ctypes.byref(b)) == HM_E_UNSUPPORTED
+        assert L.hm_workspace_size(hh, 0, 16, 0, 1, 0, ctypes.byref(b)) == HM_OK
+        assert L.hm_workspace_size(hh, 0, 16, 1, 1, 0, ctypes.byref(b)) == HM_E_UNSUPPORTED  # c128: 2^14
+        assert L.hm_set_option(hh, 1, 0) == HM_OK
+        assert L.hm_set_option(hh, 3, 3) == HM_E_ARG
+        assert L.hm_set_option(hh, 5, 14) == HM_E_ARG
+        assert L.hm_set_option(hh, 3, 4) == HM_OK
+        assert L.hm_workspace_size(hh, 0, 20, 1, 1, 0, ctypes.byref(b)) == HM_OK
+        assert L.hm_set_option(hh, 5, 13) == HM_OK  # row bits 13 leaves 6 for the column pass at n = 20
+        assert L.hm_workspace_size(hh, 0, 20, 0, 1, 0, ctypes.byref(b)) == HM_OK
+        assert L.hm_set_option(hh, 5, 6) == HM_OK   # 14 column bits: more than a column tile holds
+        assert L.hm_workspace_size(hh, 0, 21, 0, 1, 0, ctypes.byref(b)) == HM_E_UNSUPPORTED
     finally:
         L.hm_destroy(hh)
 
@@ -118,3 +150,48 @@ def test_workspace_sizes(L, h):
     assert L.hm_workspace_size(h, 0, 8, 5, 1, 0, ctypes.byref(b)) == HM_E_DTYPE
     assert L.hm_workspace_size(h, 1, 20, 0, 1, 4096, ctypes.byref(b)) == HM_OK
     assert L.hm_workspace_size(h, 2, 20, 1, 1, 0, ctypes.byref(b)) == HM_OK and b.value >= 16 << 20
+
+
+def _ws_ok(ctx_opts, n, dtype):
+    hh = P()
+    assert hm.lib().hm_create(ctypes.byref(hh)) == HM_OK
+    try:
+        for k, v in ctx_opts:
+            assert hm.lib().hm_set_option(hh, k, v) == HM_OK
+        b = ctypes.c_size_t()
+        st = hm.lib().hm_workspace_size(hh, 0, n, dtype, 1, 0, ctypes.byref(b))
+        return st, hm.lib().hm_last_error()
+    finally:
+        hm.lib().hm_destroy(hh)
+
+
+def test_planner_accepts_every_configuration_the_gpu_tests_use():
+    """Host-side planning of the forced paths and tile options exercised by the GPU parity tests."""
+    FP, BS, RRB, CRB, RB, PIPE, SPLIT = 1, 2, 3, 4, 5, 6, 7
+    cases = []
+    for rb in (0, 4):
+        for dt, n in ((1, 11), (1, 12), (1, 13), (0, 12), (0, 13), (0, 14)):
+            cases.append(([(FP, 2), (BS, 5), (RRB, rb), (CRB, rb)], n, dt))
+    for split in (1, 2):
+        for dt, n in ((1, 12), (1, 13), (1, 14), (0, 12), (0, 13), (0, 15)):
+            cases.append(([(FP, 2), (PIPE, 2), (SPLIT, split), (BS, 5)], n, dt))
+    for n in (16, 20):
+        for dt, rb, rbits, pipe in ((0, 0, 0, 0), (1, 0, 0, 0), (0, 4, 0, 0), (0, 4, 12, 0), (0, 5, 9, 0),
+                                    (0, 0, 0, 1), (0, 0, 0, 2), (1, 0, 0, 2)):
+            o = [(RRB, rb), (CRB, rb)]
+            if rbits and n == 20:
+                o.append((RB, rbits))
+            if pipe:
+                o += [(PIPE, 2), (SPLIT, pipe)]
+            cases.append((o, n, dt))
+    for dt, n in ((1, 13), (1, 14), (1, 15), (0, 14), (0, 15), (0, 16)):
+        cases.append(([(FP, 1)], n, dt))
+    cases += [([(FP, 2)], 16, 1), ([(FP, 2), (PIPE, 2)], 16, 1), ([(FP, 2), (PIPE, 2)], 16, 0)]
+    for n in range(12, 27):
+        for dt in (0, 1):
+            if dt == 1 and n > 25:
+                continue
+            cases.append(([(PIPE, 2)] if n >= 17 else [], n, dt))
+    for opts, n, dt in cases:
+        st, msg = _ws_ok(opts, n, dt)
+        assert st == HM_OK, (opts, n, dt, msg)

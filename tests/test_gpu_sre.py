@@ -5,7 +5,9 @@ FP32 transforms (complex64 input) <= 1e-5 relative on M_q (absolute 1e-5 when th
 Complex64 runs are compared with the oracle evaluated on the same complex64 values widened to
 complex128, so both sides see identical inputs.
 """
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -88,12 +90,17 @@ def test_sizes_auto_path(orc, hm, n, c64):
     assert abs(got[-1] - want[-1]) < (1e-12 if not c64 else 2e-6)
 
 
+@pytest.mark.parametrize("rb", [0, 4])
 @pytest.mark.parametrize("c64,n", [(False, 11), (False, 12), (False, 13), (True, 12), (True, 13), (True, 14)])
-def test_forced_two_pass(orc, hm, n, c64):
-    """Two-pass kernels at sizes the oracle finishes quickly; batch of 5 shifts -> ragged last batch."""
+def test_forced_two_pass(orc, hm, n, c64, rb):
+    """Two-pass kernels at sizes the oracle finishes quickly; batch of 5 shifts -> ragged last batch;
+    default and 2^4-value register tiles in both passes."""
     ctx = hm.Context()
     ctx.force_path(2)
     ctx.batch_shifts(5)
+    if rb:
+        ctx.set_option(hm.OPT_ROW_RB, rb)
+        ctx.set_option(hm.OPT_COL_RB, rb)
     psi = S.brickwall_haar(n, 2 * n, seed=3000 + n)
     for q in ((2.0,), (1.0, 2.0, 3.0)):
         say(f"[sre two-pass] n={n} c64={c64} q={q}")
@@ -101,6 +108,55 @@ def test_forced_two_pass(orc, hm, n, c64):
         got = hm.sre(x, q, ctx=ctx).cpu().numpy()
         want = orc.sre_fwht(w, q)
         assert rel_err(got[:-1], want[:-1]) < TOL[c64], (got, want)
+
+
+@pytest.mark.parametrize("split", [1, 2])
+@pytest.mark.parametrize("c64,n", [(False, 12), (False, 13), (False, 14), (True, 12), (True, 13), (True, 15)])
+def test_pipelined_two_pass(orc, hm, n, c64, split):
+    """Pipelined launches (row pass of batch k beside the column pass of batch k - 1): many ragged
+    batches, a single batch (one row-only and one column-only launch), and a partial range of two
+    batches; complex and split LDS staging."""
+    psi = S.brickwall_haar(n, 2 * n, seed=3050 + n)
+    x, w = gpu_state(psi, c64)
+    for batch, q in ((5, (2.0,)), (5, (1.0, 2.0, 3.0)), (2 ** n, (2.0,))):
+        ctx = hm.Context()
+        ctx.force_path(2)
+        ctx.set_option(hm.OPT_PIPELINE, 2)
+        ctx.set_option(hm.OPT_LDS_SPLIT, split)
+        ctx.batch_shifts(batch)
+        say(f"[sre pipelined] n={n} c64={c64} split={split} batch={batch} q={q}")
+        got = hm.sre(x, q, ctx=ctx).cpu().numpy()
+        want = orc.sre_fwht(w, q)
+        assert rel_err(got[:-1], want[:-1]) < TOL[c64], (got, want)
+        assert abs(got[-1] - want[-1]) < (1e-12 if not c64 else 2e-6)
+    ctx = hm.Context()
+    ctx.force_path(2)
+    ctx.set_option(hm.OPT_PIPELINE, 2)
+    ctx.set_option(hm.OPT_LDS_SPLIT, split)
+    ctx.batch_shifts(4)
+    got = hm.sre_partial(x, (2.0,), 3, 10, ctx=ctx).cpu().numpy()
+    want = orc.sre_fwht_sums(w, (2.0,), 3, 10)
+    np.testing.assert_allclose(got, want, rtol=(1e-11 if not c64 else 2e-6))
+
+
+@pytest.mark.parametrize("c64,n", [(False, 13), (False, 14), (False, 15), (True, 14), (True, 15), (True, 16)])
+def test_vgpr_resident_large_tiles(orc, hm, c64, n):
+    """Workgroup-resident tiles of 2^13..2^15 folded values (relayouts one component at a time),
+    checked on sampled rows of the same launch configuration and on a T-state property."""
+    ctx = hm.Context()
+    ctx.force_path(1)
+    psi = S.gaussian_state(n, seed=3150 + n)
+    x, w = gpu_state(psi, c64)
+    rows = np.concatenate([[0, 1, 2 ** n - 1, 2 ** (n - 1)], S.uniform_rows(n, 12, seed=3151)]).astype(np.int64)
+    say(f"[sre resident large] n={n} c64={c64}")
+    got = hm.sre_rows(x, rows, (2.0,), ctx=ctx).cpu().numpy()
+    want = orc.sre_rows(w, rows.astype(np.uint64), (2.0,))
+    assert rel_err(got, want, floor=1e-15) < (1e-10 if not c64 else 1e-5)
+    k = 3
+    tp = S.t_plus_clifford_state(n, k, seed=3152 + n, layers=n)
+    xt, _ = gpu_state(tp, c64)
+    m = hm.sre(xt, (2.0,), ctx=ctx).cpu().numpy()
+    assert abs(m[0] - k * math.log2(4 / 3)) < (1e-9 if not c64 else 1e-5)
 
 
 @pytest.mark.parametrize("c64", [False, True])
@@ -198,24 +254,43 @@ def test_full_size_stabilizer_and_t_states(hm, n):
 
 @pytest.mark.parametrize("n", [16, 20])
 def test_full_size_sampled_rows(orc, hm, n):
-    """Per-row sums of the launch configuration used for the full N (two-pass) vs the oracle."""
+    """Per-row sums of the launch configuration used for the full N vs the oracle (also with the
+    tile variants the planner can pick)."""
     psi = S.brickwall_haar(n, 2 * n, seed=4100 + n)
     rows = np.concatenate([[0, 1, 2 ** n - 1], S.uniform_rows(n, 13, seed=4101)]).astype(np.int64)
-    for c64 in (True, False):
+    for c64, rb, rbits, pipe in ((True, 0, 0, 0), (False, 0, 0, 0), (True, 4, 0, 0), (True, 4, 12, 0), (True, 5, 9, 0),
+                                 (True, 0, 0, 1), (True, 0, 0, 2), (False, 0, 0, 2)):
+        ctx = hm.Context()
+        if pipe:
+            ctx.set_option(hm.OPT_PIPELINE, 2)
+            ctx.set_option(hm.OPT_LDS_SPLIT, pipe)
+        if rb:
+            ctx.set_option(hm.OPT_ROW_RB, rb)
+            ctx.set_option(hm.OPT_COL_RB, rb)
+        if rbits and n == 20:
+            ctx.set_option(hm.OPT_ROW_BITS, rbits)
         x, w = gpu_state(psi, c64)
-        say(f"[sre full rows] n={n} c64={c64}")
-        got = hm.sre_rows(x, rows, (2.0,)).cpu().numpy()
+        say(f"[sre full rows] n={n} c64={c64} rb={rb} row_bits={rbits} pipe={pipe}")
+        got = hm.sre_rows(x, rows, (2.0,), ctx=ctx).cpu().numpy()
         want = orc.sre_rows(w, rows.astype(np.uint64), (2.0,))
         assert rel_err(got, want, floor=1e-15) < (1e-10 if not c64 else 1e-5)
 
 
-def test_full_size_n16_vs_oracle(orc, hm):
-    """N = 16 complex64 (two-pass) against the full FP64 oracle."""
-    n = 16
-    psi = S.brickwall_haar(n, 2 * n, seed=4200)
-    x, w = gpu_state(psi, True)
-    say("[sre n16 full] c64")
-    got = hm.sre(x, (2.0,)).cpu().numpy()
-    want = orc.sre_fwht(w, (2.0,))
-    assert rel_err(got[:1], want[:1]) < 1e-5
-    assert abs(got[1] - want[1]) < 1e-5
+def test_full_size_n16_vs_golden(hm):
+    """N = 16 against FP64 oracle values stored by tests/golden/make_golden.py (both paths)."""
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_golden.json")))
+    cases = (("sre_brickwall_n16_d32_seed4200_c64", S.brickwall_haar(16, 32, seed=4200), True, (2.0,)),
+             ("sre_gauss_n16_seed4201_c128", S.gaussian_state(16, seed=4201), False, (1.0, 2.0, 3.0)))
+    for key, psi, c64, q in cases:
+        want = np.array(gold[key]["values"])
+        # c128 holds at most 2^14 folded values per workgroup, so n = 16 is two-pass only
+        for path, pipe in (((1, 0), (2, 0), (2, 2)) if c64 else ((2, 0), (2, 2))):
+            ctx = hm.Context()
+            ctx.force_path(path)
+            if pipe:
+                ctx.set_option(hm.OPT_PIPELINE, pipe)
+            x, _ = gpu_state(psi, c64)
+            say(f"[sre n16 golden] {key} path={path} pipe={pipe}")
+            got = hm.sre(x, q, ctx=ctx).cpu().numpy()
+            assert rel_err(got[:-1], want[:-1]) < (1e-5 if c64 else 1e-10), (got, want)
+            assert abs(got[-1] - want[-1]) < (1e-5 if c64 else 1e-12)
