@@ -39,6 +39,47 @@ def sre_kernel_mix(N: int, family: str, nl: int, nh: int):
     return None
 
 
+def PROFILE_EVERY(N: int, shifts: int) -> int:
+    """Sampling interval of the kernel timing: about 256 timed launches per family and step."""
+    per_launch = max(1, (128 << 20) // (8 << max(N - 1, 0)))  # shifts per two-pass launch, roughly
+    return max(1, shifts // per_launch // 256)
+
+
+HBM_PEAK_GBS = 8000.0
+
+
+def roofline(fam: str, N: int, vals_per_launch: float, t_launch: float, launches_per_step: int):
+    """Roofline of one kernel family (complex64).  Two-pass kernels move the half-transformed vector
+    through device memory (8 B per folded value written by the row pass and read by the column
+    pass; the pipelined kernel does both): that compulsory exchange is their bound.  The
+    workgroup-resident kernel touches device memory only for the state and is bound by FP32 VALU
+    arithmetic."""
+    nf = N - 1
+    nl = (nf + 1) // 2
+    nh = nf - nl
+    xbytes = {"sre_rowpass_write": 8.0, "sre_colpass": 8.0, "sre_pair": 16.0}.get(fam)
+    mix = sre_kernel_mix(N, fam if fam != "sre_pair" else "sre_rowpass_write", nl, nh)
+    r = {"kernel": fam, "launches_per_step": launches_per_step, "avg_launch_ms": round(t_launch * 1e3, 5)}
+    valu = None
+    if mix:
+        flops_per_val, ops_per_val = mix
+        achieved = vals_per_launch * flops_per_val / t_launch / 1e12
+        peak = LANE_OPS_PER_S * flops_per_val / ops_per_val / 1e12
+        valu = {"achieved": round(achieved, 2), "peak": round(peak, 2), "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4)}
+    if xbytes:
+        bpl = vals_per_launch * xbytes
+        achieved = bpl / t_launch / 1e9
+        r.update({"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_launch": bpl,
+                  "traffic": traffic_for(fam, f"sre_n{N}_c64"), "valu": valu,
+                  "note": "achieved = exchange bytes (8 B per folded value per pass) / average launch time"})
+    elif valu:
+        r.update({"bound": "alu", **valu, "traffic": traffic_for(fam, f"sre_n{N}_c64"),
+                  "note": "FP32 VALU without packed FP32: 39.3e12 lane-ops/s x flops per op of this kernel"})
+    return r
+
+
 def traffic_for(kernel: str, workload: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if the kernel source is
     unchanged since the counters were taken."""
@@ -72,6 +113,62 @@ def cpu_baseline(psi_w, N: int, target_s: float = 12.0):
                       f"{k2 * 2 ** N:.3e} expectations, {dt:.1f} s, FP64 C + OpenMP)"}
 
 
+def _timed(torch, fn, reps=1):
+    fn()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        o = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t) / reps, o
+
+
+def secondary(hm, S, torch, dev, psi, N):
+    """The other rows of the metric, each timed once after a warm-up call (wall clock around the
+    call, state resident): complex128 forward at the headline N, mana at N = 12, fused
+    forward + adjoint against the plain forwards at N = 13 (workgroup-resident gradient), the
+    batched form on 1024 states of uneven size, and the Monte Carlo estimator at N = 24."""
+    import numpy as np
+    sec = {}
+    try:
+        x128 = torch.from_numpy(psi).to(dev)
+        dt, o = _timed(torch, lambda: hm.sre(x128, (2.0,)))
+        sec["sre_fwd_c128_n%d" % N] = {"value": 4.0 ** N / dt, "unit": "Pauli expectations/s", "ms": dt * 1e3,
+                                        "M2": float(o[0].item())}
+        del x128
+        m = torch.from_numpy(S.to_c64_exact(S.gaussian_state(12, d=3, seed=1212))[0]).to(dev)
+        dt, o = _timed(torch, lambda: hm.mana(m))
+        sec["mana_n12_c64"] = {"value": 9.0 ** 12 / dt, "unit": "phase-space points/s", "ms": dt * 1e3,
+                               "mana": float(o[0].item())}
+        ng = 13
+        pg = S.ry_rz_cz_state(ng, np.random.default_rng(4013).uniform(0, 2 * math.pi, (2, 2, ng)))
+        g64 = torch.from_numpy(S.to_c64_exact(pg)[0]).to(dev)
+        g128 = torch.from_numpy(pg).to(dev)
+        for key, fn in (("sre_fwd_grad_c64_n13", lambda: hm.sre_grad(g64, 2.0)),
+                        ("sre_fwd_c64_n13", lambda: hm.sre(g64, (2.0,))),
+                        ("sre_fwd_c128_n13", lambda: hm.sre(g128, (2.0,)))):
+            dt, _ = _timed(torch, fn, reps=20)
+            sec[key] = {"value": 4.0 ** ng / dt, "unit": "Pauli expectations/s", "ms": dt * 1e3}
+        rng = np.random.default_rng(5005)
+        ns = rng.integers(10, 17, size=1024)
+        states = [torch.from_numpy(S.to_c64_exact(S.gaussian_state(int(n), seed=5000 + i))[0]).to(dev)
+                  for i, n in enumerate(ns)]
+        dt, _ = _timed(torch, lambda: hm.sre_batched(states, (2.0,)))
+        sec["sre_batched_1024_n10to16_c64"] = {"value": float(np.sum(4.0 ** ns)) / dt, "unit": "Pauli expectations/s",
+                                               "ms": dt * 1e3, "states": 1024}
+        del states
+        g = torch.Generator(device="cpu").manual_seed(2424)
+        v = torch.view_as_complex(torch.randn(2 ** 24, 2, generator=g, dtype=torch.float32)).to(dev)
+        v /= torch.linalg.vector_norm(v)
+        dt, o = _timed(torch, lambda: hm.sre_sampled(v, n_rows=4096, seed=24))
+        sec["sre_mc_n24_4096rows_c64"] = {"value": 4097 * 2.0 ** 24 / dt, "unit": "Pauli expectations/s",
+                                          "ms": dt * 1e3, "M2_hat": float(o[0].item()),
+                                          "stderr": float(o[1].item())}
+    except hm.HmError as e:
+        sec["error"] = str(e)[:200]
+    return sec
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +177,14 @@ def main():
     ap.add_argument("--n", type=int, default=20, help="qubits (default 20)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--shifts", type=int, default=0,
+                    help="profiling runs: evaluate only X-shifts [0, SHIFTS) per step (0 = all 2^N)")
+    ap.add_argument("--batch", type=int, default=0, help="X-shifts per two-pass launch (0 = planner default)")
+    ap.add_argument("--pipeline", type=int, default=0, choices=(0, 1, 2), help="HM_OPT_PIPELINE")
+    ap.add_argument("--lds-split", type=int, default=0, choices=(0, 1, 2), help="HM_OPT_LDS_SPLIT")
+    ap.add_argument("--no-autotune", action="store_true", help="skip the plan autotuner (untimed, before warm-up)")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="counter calibration: time a plain device copy of this many MiB five times and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the X-shift loop "
@@ -94,52 +199,67 @@ def main():
     from synth import states as S
 
     dev = torch.device("cuda:0")
+    if args.copy_mib:
+        n = args.copy_mib << 18  # float32 elements
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_mib": args.copy_mib, "launches": 5}), flush=True)
+        return
     N = args.n
     seed = 2020
     psi = S.brickwall_haar(N, 2 * N, seed=seed)
     c64, c64w = S.to_c64_exact(psi)
     x = torch.from_numpy(c64).to(dev)
-    ctx = hm.default_context()
+    ctx = hm.Context()
+    if args.batch:
+        ctx.batch_shifts(args.batch)
+    if args.pipeline:
+        ctx.set_option(hm.OPT_PIPELINE, args.pipeline)
+    if args.lds_split:
+        ctx.set_option(hm.OPT_LDS_SPLIT, args.lds_split)
+    shifts = args.shifts if args.shifts else 2 ** N
+    plan = None
+    if not args.no_autotune and not (args.batch or args.pipeline or args.lds_split):
+        t = time.perf_counter()
+        plan = hm.autotune(x, 16384, ctx=ctx)
+        plan["tune_s"] = round(time.perf_counter() - t, 3)
+
+    def step():
+        if args.shifts:
+            return hm.sre_partial(x, (2.0,), 0, shifts, ctx=ctx)
+        return hm.sre(x, (2.0,), ctx=ctx)
 
     for _ in range(args.warmup):
-        hm.sre(x, (2.0,))
+        step()
     torch.cuda.synchronize()
 
+    # Kernel timing inside the timed region: hipEvents on the launch stream around every k-th launch
+    # of each kernel family (k chosen so that a few hundred launches per family are timed).
     hm.profile_reset()
-    hm.profile_enable(True)
+    hm.profile_enable(PROFILE_EVERY(N, shifts))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        out = hm.sre(x, (2.0,))
+        out = step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     hm.profile_enable(False)
     prof = hm.profile_read()
     ms = (t1 - t0) * 1e3 / args.steps
     res = out.cpu().numpy()
-    value = float(4 ** N) / (ms * 1e-3)
+    work = float(shifts) * float(2 ** N)  # Pauli expectations per step
+    value = work / (ms * 1e-3)
 
-    # dominant kernel and its roofline
-    nf = N - 1
-    nl = (nf + 1) // 2
-    nh = nf - nl
-    fam = max(prof, key=lambda k: prof[k][1])
-    cnt, tot_ms = prof[fam]
-    mix = sre_kernel_mix(N, fam, nl, nh)
-    roof = None
-    if mix:
-        flops_per_val, ops_per_val = mix
-        vals_per_launch = float(2 ** N) * float(2 ** nf) / cnt / args.steps * args.steps  # per launch
-        vals_per_launch = float(2 ** N) * float(2 ** nf) * args.steps / cnt
-        t_launch = tot_ms * 1e-3 / cnt
-        achieved = vals_per_launch * flops_per_val / t_launch / 1e12
-        peak = LANE_OPS_PER_S * flops_per_val / ops_per_val / 1e12
-        roof = {"bound": "alu", "kernel": fam, "achieved": round(achieved, 2), "peak": round(peak, 2),
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                "traffic": traffic_for(fam, f"sre_n{N}_c64"),
-                "launches": cnt, "avg_launch_ms": round(tot_ms / cnt, 4),
-                "flops_per_launch": vals_per_launch * flops_per_val,
-                "note": "FP32 VALU, no packed FP32: 39.3e12 lane-ops/s x (flops/op of this kernel's mix)"}
+    # dominant kernel (largest estimated device time per step) and its roofline
+    est = {k: v[2] / max(v[1], 1) * v[0] for k, v in prof.items() if v[1] > 0}
+    fam = max(est, key=est.get)
+    launches, timed, tot_ms = prof[fam]
+    t_launch = tot_ms * 1e-3 / timed
+    vals_per_launch = work / 2.0 * args.steps / launches  # folded values per launch
+    roof = roofline(fam, N, vals_per_launch, t_launch, launches // args.steps)
 
     line = {
         "metric": "Pauli expectations/s for M_2 (N=20 qubits) & mana (N=12); fwd vs fwd+grad",
@@ -147,39 +267,18 @@ def main():
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "c64 (fp32 transforms, fp64 sums)", "data": "synthetic",
         "config": {"workload": f"SRE M_2, N={N} qubits, complex64, brick-wall Haar circuit depth {2 * N}, seed {seed}, "
-                               f"all 4^{N} Pauli strings", "parallelism": "none (1 GPU)"},
-        "result": {"M2": float(res[0]), "lost_norm": float(res[1])},
-        "kernel_ms": {k: round(v[1] / args.steps, 3) for k, v in prof.items()},
+                               + (f"all 4^{N} Pauli strings" if not args.shifts else
+                                  f"X-shifts [0, {shifts}) x 2^{N} Z-strings (profiling subset)"),
+                   "parallelism": "none (1 GPU)"},
+        "result": ({"M2": float(res[0]), "lost_norm": float(res[1])} if not args.shifts else
+                   {"partial_sums": [float(v) for v in res]}),
+        "kernel_ms_per_step": {k: round(est[k] / args.steps, 3) for k in est},
         "roofline": roof,
+        "plan": plan,
     }
 
-    if not args.no_secondary:
-        sec = {}
-        # complex128 (FP64 transforms) forward on the same state
-        x128 = torch.from_numpy(psi).to(dev)
-        hm.sre(x128, (2.0,))
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        o = hm.sre(x128, (2.0,))
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t
-        sec["sre_fwd_c128"] = {"value": float(4 ** N) / dt, "ms": dt * 1e3, "M2": float(o[0].item())}
-        for key, fn in (("mana_n12_c64", lambda: hm.mana(torch.from_numpy(
-                S.to_c64_exact(S.gaussian_state(12, d=3, seed=1212))[0]).to(dev))),
-                        ("sre_fwd_grad_c64", lambda: hm.sre_grad(x, 2.0))):
-            try:
-                fn()
-                torch.cuda.synchronize()
-                t = time.perf_counter()
-                o = fn()
-                torch.cuda.synchronize()
-                dt = time.perf_counter() - t
-                work = 9.0 ** 12 if key.startswith("mana") else 4.0 ** N
-                sec[key] = {"value": work / dt, "ms": dt * 1e3,
-                            "unit": "phase-space points/s" if key.startswith("mana") else "Pauli expectations/s"}
-            except hm.HmError as e:
-                sec[key] = {"value": None, "error": str(e)[:160]}
-        line["secondary"] = sec
+    if not args.no_secondary and not args.shifts:
+        line["secondary"] = secondary(hm, S, torch, dev, psi, N)
 
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(c64w, N)

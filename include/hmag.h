@@ -78,8 +78,9 @@ const char *hm_version(void);
  *   HM_OPT_PIPELINE: two-pass launches, 1 = one row pass then one column pass per batch of
  *     shifts, 2 = pipelined (each launch runs the row pass of batch k beside the column pass of
  *     batch k - 1, with two exchange buffers; default tiles and split only).
- *   HM_OPT_LDS_SPLIT: pipelined kernels only, 1 = stage complex values through LDS, 2 = stage
- *     real and imaginary parts one after the other (half the LDS per workgroup).
+ *   HM_OPT_LDS_SPLIT: two-pass kernels with the default register tiles, 1 = stage complex values
+ *     through LDS, 2 = stage real and imaginary parts one after the other (half the LDS per
+ *     workgroup, so more workgroups per CU).
  * A combination outside the built kernels makes the SRE calls return HM_E_UNSUPPORTED. */
 typedef enum {
   HM_OPT_FORCE_PATH = 1,
@@ -91,6 +92,25 @@ typedef enum {
   HM_OPT_LDS_SPLIT = 7
 } hm_option;
 hm_status hm_set_option(hm_handle h, hm_option opt, int64_t value);
+
+/* Autotuner.  Times every candidate SRE plan for (n, dtype) on the state psi (device) over the
+ * first sample_shifts X-shifts (16384 if <= 0, at most 2^n): the workgroup-resident kernel where it
+ * applies, and two-pass plans over exchange batches of 64/128/256 MiB, both LDS stagings,
+ * sequential launches with the default, 11 or 12 row bits, and pipelined launches.  Options
+ * already set on the handle are kept fixed.  The fastest plan is stored in the handle; later calls
+ * on the handle for the same (n, dtype) fill every option left automatic from it.  Candidates
+ * whose workspace exceeds ws_bytes are skipped (hm_autotune_workspace gives the size that admits
+ * all of them).  Blocks until the timings are done (it synchronises on events on `stream`).
+ * Results of the sampled shifts are discarded. */
+hm_status hm_autotune_workspace(hm_handle h, int n, hm_dtype dtype, int64_t sample_shifts, size_t *bytes);
+hm_status hm_autotune(hm_handle h, const void *psi, int n, hm_dtype dtype, int64_t sample_shifts, void *ws,
+                      size_t ws_bytes, hipStream_t stream);
+/* The stored plan for (n, dtype): opts[0..6] = {HM_OPT_FORCE_PATH, HM_OPT_BATCH_SHIFTS,
+ * HM_OPT_ROW_RB, HM_OPT_COL_RB, HM_OPT_ROW_BITS, HM_OPT_PIPELINE, HM_OPT_LDS_SPLIT} values (host
+ * array of 7), and its measured milliseconds per X-shift.  HM_E_ARG if none is stored. */
+hm_status hm_tune_query(hm_handle h, int n, hm_dtype dtype, int64_t *opts, double *ms_per_shift);
+/* Forgets every stored plan of the handle. */
+hm_status hm_tune_clear(hm_handle h);
 
 /* ------------------------------------------------------------------------------------------ */
 /* Workspace sizes.  Each entry point needs a device workspace of at least the returned size.   */
@@ -200,10 +220,12 @@ hm_status hm_mana_partial(hm_handle h, const void *psi, int n, hm_dtype dtype, u
 hm_status hm_profile_enable(int every);
 /* Drops the accumulated timings. */
 hm_status hm_profile_reset(void);
-/* Timing of kernel family `index` (0-based, in order of first launch): its name (NUL-terminated,
- * truncated to name_len), number of launches and summed device milliseconds.  Synchronises with
- * the recorded events.  HM_E_ARG once index passes the last family. */
-hm_status hm_profile_query(int index, char *name, size_t name_len, int64_t *count, double *ms);
+/* Kernel family `index` (0-based, in order of first launch since the last reset): its name
+ * (NUL-terminated, truncated to name_len), the number of its launches, the number of those that
+ * were timed and their summed device milliseconds.  Synchronises with the recorded events.  Any
+ * output pointer may be NULL.  HM_E_ARG once index passes the last family. */
+hm_status hm_profile_query(int index, char *name, size_t name_len, int64_t *launches, int64_t *timed,
+                           double *ms);
 
 #ifdef __cplusplus
 }

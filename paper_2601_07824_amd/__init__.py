@@ -18,7 +18,7 @@ from typing import Sequence
 
 __all__ = [
     "HmError", "lib", "lib_path", "Context", "default_context", "sre", "sre_partial", "sre_finalize",
-    "sre_rows", "sre_row_values", "sre_grad", "SRE", "sre_batched", "sre_sampled", "mana", "mana_partial", "workspace_size",
+    "sre_rows", "sre_row_values", "sre_grad", "SRE", "sre_batched", "sre_sampled", "autotune", "tuned_plan", "mana", "mana_partial", "workspace_size",
     "HM_C64", "HM_C128", "profile_enable", "profile_reset", "profile_read", "OP_SRE", "OP_SRE_ROWS", "OP_ROW_VALUES", "OP_SRE_GRAD", "OP_MANA",
     "EXPORTED_SYMBOLS",
 ]
@@ -57,9 +57,13 @@ _SIGS = {
     "hm_sre_batched_workspace": (_i, [_vp, ctypes.POINTER(_i), _i, _i, _i, ctypes.POINTER(_sz)]),
     "hm_sre_batched": (_i, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_i), _i, _i, _dp, _i, _vp, _vp, _sz, _vp]),
     "hm_sre_sampled": (_i, [_vp, _vp, _i, _i, _vp, _i64, _vp, _vp, _sz, _vp]),
+    "hm_autotune_workspace": (_i, [_vp, _i, _i, _i64, ctypes.POINTER(_sz)]),
+    "hm_autotune": (_i, [_vp, _vp, _i, _i, _i64, _vp, _sz, _vp]),
+    "hm_tune_query": (_i, [_vp, _i, _i, ctypes.POINTER(_i64), _dp]),
+    "hm_tune_clear": (_i, [_vp]),
     "hm_profile_enable": (_i, [_i]),
     "hm_profile_reset": (_i, []),
-    "hm_profile_query": (_i, [_i, ctypes.c_char_p, _sz, ctypes.POINTER(_i64), _dp]),
+    "hm_profile_query": (_i, [_i, ctypes.c_char_p, _sz, ctypes.POINTER(_i64), ctypes.POINTER(_i64), _dp]),
 }
 EXPORTED_SYMBOLS = tuple(_SIGS)
 
@@ -206,16 +210,17 @@ def profile_reset():
 
 
 def profile_read() -> dict:
-    """{kernel family: (launches, total device ms)} accumulated since the last reset."""
+    """{kernel family: (launches, timed launches, total device ms of the timed ones)} since the
+    last reset."""
     out = {}
     i = 0
     buf = ctypes.create_string_buffer(128)
     while True:
-        c, ms = _i64(0), ctypes.c_double(0.0)
-        st = lib().hm_profile_query(i, buf, 128, ctypes.byref(c), ctypes.byref(ms))
+        n, c, ms = _i64(0), _i64(0), ctypes.c_double(0.0)
+        st = lib().hm_profile_query(i, buf, 128, ctypes.byref(n), ctypes.byref(c), ctypes.byref(ms))
         if st != 0:
             break
-        out[buf.value.decode()] = (c.value, ms.value)
+        out[buf.value.decode()] = (n.value, c.value, ms.value)
         i += 1
     return out
 
@@ -276,6 +281,33 @@ def sre_rows(psi, rows, q=(2.0,), *, ctx: Context | None = None, stream=None):
     _check(lib().hm_sre_rows(ctx.h, _ptr(psi), n, dt, _ptr(rows), nr, qa, nq, _ptr(out), _ptr(ws), ws.numel(),
                              _stream(stream)))
     return out
+
+
+TUNE_KEYS = ("force_path", "batch_shifts", "row_rb", "col_rb", "row_bits", "pipeline", "lds_split")
+
+
+def autotune(psi, sample_shifts: int = 16384, *, ctx: Context | None = None, stream=None) -> dict:
+    """Time the candidate SRE plans for this state's size and dtype on the device, keep the fastest
+    in the context (used from then on for options left automatic) and return it."""
+    ctx = ctx or default_context()
+    psi, n = _state(psi, 2)
+    dt = _dtype_code(psi)
+    b = _sz(0)
+    _check(lib().hm_autotune_workspace(ctx.h, n, dt, sample_shifts, ctypes.byref(b)))
+    ws = _workspace(b.value, psi.device)
+    _check(lib().hm_autotune(ctx.h, _ptr(psi), n, dt, sample_shifts, _ptr(ws), ws.numel(), _stream(stream)))
+    return tuned_plan(n, dt, ctx=ctx)
+
+
+def tuned_plan(n: int, dtype_code: int, *, ctx: Context | None = None) -> dict:
+    """The plan the autotuner stored for (n, dtype code), with its milliseconds per X-shift."""
+    ctx = ctx or default_context()
+    v = (_i64 * 7)()
+    ms = ctypes.c_double(0.0)
+    _check(lib().hm_tune_query(ctx.h, n, dtype_code, v, ctypes.byref(ms)))
+    d = dict(zip(TUNE_KEYS, [int(x) for x in v]))
+    d["ms_per_shift"] = ms.value
+    return d
 
 
 def sre_batched(states, q=(2.0,), *, ctx: Context | None = None, stream=None):

@@ -15,9 +15,6 @@
 
 #define HM_VERSION_STRING "hmag 0.1.0 (gfx950)"
 
-struct hm_context {
-  hm::PlanOpts opts;
-};
 
 namespace hm {
 
@@ -162,7 +159,7 @@ hm_status hm_workspace_size(hm_handle h, hm_op op, int n, hm_dtype dtype, int n_
     case HM_OP_SRE: {
       if (n_q < 1 || n_q > HM_MAX_Q) return (hm_status)fail(E_ARG, "n_q = %d outside [1, %d]", n_q, HM_MAX_Q);
       SrePlan p;
-      HM_TRY(sre_plan(n, dbl, h->opts, &p));
+      HM_TRY(sre_plan(n, dbl, plan_opts(h, n, dbl), &p));
       *bytes = sre_workspace(p, n_q, (int64_t)1 << n);
       return HM_OK;
     }
@@ -170,7 +167,7 @@ hm_status hm_workspace_size(hm_handle h, hm_op op, int n, hm_dtype dtype, int n_
       if (n_q < 1 || n_q > HM_MAX_Q) return (hm_status)fail(E_ARG, "n_q = %d outside [1, %d]", n_q, HM_MAX_Q);
       if (count < 0) return (hm_status)fail(E_ARG, "count = %lld < 0", (long long)count);
       SrePlan p;
-      HM_TRY(sre_plan(n, dbl, h->opts, &p));
+      HM_TRY(sre_plan(n, dbl, plan_opts(h, n, dbl), &p));
       *bytes = sre_workspace(p, n_q, 0);
       return HM_OK;
     }
@@ -185,7 +182,7 @@ hm_status hm_workspace_size(hm_handle h, hm_op op, int n, hm_dtype dtype, int n_
     case HM_OP_SRE_SAMPLED: {
       if (count < 2) return (hm_status)fail(E_ARG, "sampled: count = %lld < 2", (long long)count);
       SrePlan p;
-      HM_TRY(sre_plan(n, dbl, h->opts, &p));
+      HM_TRY(sre_plan(n, dbl, plan_opts(h, n, dbl), &p));
       *bytes = align256((size_t)(count + 1) * 2 * sizeof(double)) + sre_workspace(p, 1, 0);
       return HM_OK;
     }
@@ -210,7 +207,7 @@ hm_status hm_sre(hm_handle h, const void *psi, int n, hm_dtype dtype, const doub
   QArgs qa;
   HM_TRY(check_q(q, n_q, &qa));
   SrePlan p;
-  HM_TRY(sre_plan(n, dtype == HM_C128, h->opts, &p));
+  HM_TRY(sre_plan(n, dtype == HM_C128, plan_opts(h, n, dtype == HM_C128), &p));
   const int64_t n_shifts = (int64_t)1 << n;
   HM_TRY(check_ws(ws, ws_bytes, sre_workspace(p, n_q, n_shifts)));
   return (hm_status)sre_run(p, psi, qa, 0, nullptr, n_shifts, nullptr, nullptr, out, ws, stream);
@@ -226,7 +223,7 @@ hm_status hm_sre_partial(hm_handle h, const void *psi, int n, hm_dtype dtype, co
   QArgs qa;
   HM_TRY(check_q(q, n_q, &qa));
   SrePlan p;
-  HM_TRY(sre_plan(n, dtype == HM_C128, h->opts, &p));
+  HM_TRY(sre_plan(n, dtype == HM_C128, plan_opts(h, n, dtype == HM_C128), &p));
   const uint64_t D = 1ull << n;
   if (a0 > a1 || a1 > D) return (hm_status)fail(E_ARG, "shift range [%llu, %llu) not inside [0, 2^%d]", (unsigned long long)a0, (unsigned long long)a1, n);
   const int64_t n_slots = (int64_t)(a1 - a0);
@@ -255,7 +252,7 @@ hm_status hm_sre_rows(hm_handle h, const void *psi, int n, hm_dtype dtype, const
   QArgs qa;
   HM_TRY(check_q(q, n_q, &qa));
   SrePlan p;
-  HM_TRY(sre_plan(n, dtype == HM_C128, h->opts, &p));
+  HM_TRY(sre_plan(n, dtype == HM_C128, plan_opts(h, n, dtype == HM_C128), &p));
   if (n_rows == 0) return HM_OK;
   HM_TRY(check_ptr(rows, 8, "rows"));
   HM_TRY(check_ptr(row_sums, 8, "row_sums"));
@@ -296,7 +293,7 @@ static int batched_ws(hm_handle h, const int *ns, int batch, int dbl, int n_q, s
   size_t need = 256;
   for (int i = 0; i < batch; ++i) {
     SrePlan p;
-    int st = sre_plan(ns[i], dbl, h->opts, &p);
+    int st = sre_plan(ns[i], dbl, plan_opts(h, ns[i], dbl), &p);
     if (st) return st;
     size_t b;
     if (p.path == 1) {
@@ -339,7 +336,7 @@ hm_status hm_sre_batched(hm_handle h, const void *const *psis, const int *ns, in
   for (int i = 0; i < batch; ++i) {
     if (done[i]) continue;
     SrePlan p;
-    HM_TRY(sre_plan(ns[i], dbl, h->opts, &p));
+    HM_TRY(sre_plan(ns[i], dbl, plan_opts(h, ns[i], dbl), &p));
     if (p.path != 1) {
       done[i] = 1;
       HM_TRY(sre_run(p, psis[i], qa, 0, nullptr, (int64_t)1 << ns[i], nullptr, nullptr, out + (size_t)i * (n_q + 1), ws,
@@ -377,7 +374,7 @@ hm_status hm_sre_sampled(hm_handle h, const void *psi, int n, hm_dtype dtype, co
   const double q2 = 2.0;
   HM_TRY(check_q(&q2, 1, &qa));
   SrePlan p;
-  HM_TRY(sre_plan(n, dtype == HM_C128, h->opts, &p));
+  HM_TRY(sre_plan(n, dtype == HM_C128, plan_opts(h, n, dtype == HM_C128), &p));
   const size_t rs_bytes = align256((size_t)(n_rows + 1) * 2 * sizeof(double));
   HM_TRY(check_ws(ws, ws_bytes, rs_bytes + sre_workspace(p, 1, 0)));
   double *rs = (double *)ws;
@@ -385,6 +382,48 @@ hm_status hm_sre_sampled(hm_handle h, const void *psi, int n, hm_dtype dtype, co
   HM_TRY(sre_run(p, psi, qa, 0, nullptr, 1, s0, nullptr, nullptr, (char *)ws + rs_bytes, stream));
   HM_TRY(sre_run(p, psi, qa, 0, rows, n_rows, rs, nullptr, nullptr, (char *)ws + rs_bytes, stream));
   return (hm_status)sre_sampled_stats(rs, rows, n_rows, 2, s0, n, out, stream);
+}
+
+hm_status hm_autotune_workspace(hm_handle h, int n, hm_dtype dtype, int64_t sample_shifts, size_t *bytes) {
+  g_err[0] = 0;
+  if (!h || !bytes) return (hm_status)fail(E_ARG, "h or bytes is NULL");
+  HM_TRY(check_dtype(dtype));
+  if (n < 1 || n > 26) return (hm_status)fail(E_SIZE, "autotune: n = %d outside [1, 26]", n);
+  *bytes = sre_autotune_workspace(h, n, dtype == HM_C128, sample_shifts);
+  return HM_OK;
+}
+
+hm_status hm_autotune(hm_handle h, const void *psi, int n, hm_dtype dtype, int64_t sample_shifts, void *ws,
+                      size_t ws_bytes, hipStream_t stream) {
+  g_err[0] = 0;
+  if (!h) return (hm_status)fail(E_ARG, "h is NULL");
+  HM_TRY(check_dtype(dtype));
+  if (n < 1 || n > 26) return (hm_status)fail(E_SIZE, "autotune: n = %d outside [1, 26]", n);
+  HM_TRY(check_ptr(psi, psi_align(dtype), "psi"));
+  HM_TRY(check_ws(ws, ws_bytes, 256));
+  return (hm_status)sre_autotune(h, psi, n, dtype == HM_C128, sample_shifts, ws, ws_bytes, stream, nullptr);
+}
+
+hm_status hm_tune_query(hm_handle h, int n, hm_dtype dtype, int64_t *opts, double *ms_per_shift) {
+  g_err[0] = 0;
+  if (!h || !opts) return (hm_status)fail(E_ARG, "h or opts is NULL");
+  HM_TRY(check_dtype(dtype));
+  for (const auto &t : h->tuned)
+    if (t.n == n && t.dbl == (dtype == HM_C128)) {
+      const PlanOpts &o = t.opts;
+      const int64_t v[7] = {o.force_path, o.batch, o.row_rb, o.col_rb, o.row_bits, o.pipeline, o.lds_split};
+      for (int i = 0; i < 7; ++i) opts[i] = v[i];
+      if (ms_per_shift) *ms_per_shift = t.ms_per_shift;
+      return HM_OK;
+    }
+  return (hm_status)fail(E_ARG, "no autotuned plan for n = %d on this handle", n);
+}
+
+hm_status hm_tune_clear(hm_handle h) {
+  g_err[0] = 0;
+  if (!h) return (hm_status)fail(E_ARG, "h is NULL");
+  h->tuned.clear();
+  return HM_OK;
 }
 
 hm_status hm_mana(hm_handle h, const void *psi, int n, hm_dtype dtype, double *out, void *ws, size_t ws_bytes,

@@ -4,6 +4,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 #ifndef HM_MAX_Q
 #define HM_MAX_Q 8
 #endif
@@ -87,6 +89,34 @@ struct PlanOpts {
   int pipeline = 0;  // 0 automatic, 1 off, 2 on
   int lds_split = 0; // 0 automatic, 1 off, 2 on
 };
+
+// Plan options chosen by the autotuner for one (qubit count, dtype).
+struct TunedPlan {
+  int n;
+  int dbl;
+  PlanOpts opts;
+  double ms_per_shift;
+};
+
+}  // namespace hm
+
+// The handle: options set by the caller and the autotuner's table.
+struct hm_context {
+  hm::PlanOpts opts;
+  std::vector<hm::TunedPlan> tuned;
+};
+
+namespace hm {
+
+// Autotuner: times the candidate plans for (n, dbl) on psi over the first `sample` X-shifts
+// (16384 if <= 0, at most 2^n) and records the fastest in h->tuned.  Blocks until done.
+int sre_autotune(hm_context *h, const void *psi, int n, int dbl, int64_t sample, void *ws, size_t ws_bytes,
+                 hipStream_t st, TunedPlan *best);
+size_t sre_autotune_workspace(const hm_context *h, int n, int dbl, int64_t sample);
+
+// Options for planning (n, dbl) on handle h: every field the caller left automatic (0) is taken
+// from the autotuner's entry for (n, dbl), if there is one.
+PlanOpts plan_opts(const hm_context *h, int n, int dbl);
 
 // Fills a plan; returns OK or E_UNSUPPORTED/E_SIZE with a message.
 int sre_plan(int N, int dbl, const PlanOpts &o, SrePlan *p);

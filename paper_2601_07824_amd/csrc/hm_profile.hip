@@ -110,17 +110,26 @@ hm_status hm_profile_reset(void) {
   return HM_OK;
 }
 
-hm_status hm_profile_query(int index, char *name, size_t name_len, int64_t *count, double *ms) {
+hm_status hm_profile_query(int index, char *name, size_t name_len, int64_t *launches, int64_t *timed, double *ms) {
   std::lock_guard<std::mutex> g(hm::g_mu);
   hm::harvest();
-  if (index < 0 || index >= (int)hm::g_tot.size()) return (hm_status)hm::fail(hm::E_ARG, "profile index %d out of range", index);
-  const auto &t = hm::g_tot[index];
+  if (index < 0 || index >= (int)hm::g_seen.size())
+    return (hm_status)hm::fail(hm::E_ARG, "profile index %d out of range", index);
+  const auto &f = hm::g_seen[index];
+  int64_t c = 0;
+  double t = 0.0;
+  for (const auto &r : hm::g_tot)
+    if (r.name == f.name) {
+      c = r.count;
+      t = r.ms;
+    }
   if (name && name_len) {
-    strncpy(name, t.name.c_str(), name_len - 1);
+    strncpy(name, f.name.c_str(), name_len - 1);
     name[name_len - 1] = 0;
   }
-  if (count) *count = t.count;
-  if (ms) *ms = t.ms;
+  if (launches) *launches = f.seen;
+  if (timed) *timed = c;
+  if (ms) *ms = t;
   return HM_OK;
 }
 

@@ -160,8 +160,8 @@ __global__ __launch_bounds__(256) void k_sre_total(const double *shift_sums, int
 // two-pass split puts ceil(nf / 2) index bits in the row pass.  Every choice can be overridden
 // through PlanOpts (options of the handle) and is validated against the built kernels here.
 // Pipelined launches (row pass of batch k with the column pass of batch k - 1) and split LDS staging
-// are used automatically when these are set.
-static constexpr bool SRE_PIPE_DEFAULT = false, SRE_SPLIT_DEFAULT = false;
+// (two-pass kernels) are used automatically when these are set.
+static constexpr bool SRE_PIPE_DEFAULT = false, SRE_SPLIT_DEFAULT = true;
 
 int sre_plan(int N, int dbl, const PlanOpts &o, SrePlan *p) {
   if (N < 1 || N > 26) return fail(E_SIZE, "SRE: n = %d outside [1, 26]", N);
@@ -196,16 +196,22 @@ int sre_plan(int N, int dbl, const PlanOpts &o, SrePlan *p) {
     P.col_tb = col_tb;
     P.row_rb = row_rb;
     P.col_rb = col_rb;
-    // The exchange of one batch (batch x 2^nf values) is sized to stay resident in the 256 MiB
-    // memory-side cache (MALL) while giving each launch enough tiles to fill the 256 CUs.
     // Pipelined launches keep two exchange buffers in flight (one written, one read).
     P.pipe = 0;
     if (o.pipeline == 2 && !sre_pipe_built(P))
       return fail(E_UNSUPPORTED, "SRE: no pipelined kernels for n = %d with these tiles", N);
     if (o.pipeline == 2 || (o.pipeline == 0 && SRE_PIPE_DEFAULT && sre_pipe_built(P))) P.pipe = 1;
-    P.split = P.pipe && (o.lds_split == 2 || (o.lds_split == 0 && SRE_SPLIT_DEFAULT));
+    // Split LDS staging (half the LDS per workgroup) exists for the default register tiles only.
+    const bool split_ok = row_rb == RB && col_rb == RB;
+    if (o.lds_split == 2 && !split_ok)
+      return fail(E_UNSUPPORTED, "SRE: split LDS staging needs the default register tiles (2^%d)", RB);
+    P.split = split_ok && (o.lds_split == 2 || (o.lds_split == 0 && !dbl && SRE_SPLIT_DEFAULT));
+    // Untuned batch: 256 MiB of exchange per FP32 launch (measured best at n = 20 on MI355X: the
+    // launch count matters more than staying inside the 256 MiB MALL), 128 MiB for FP64; pipelined
+    // launches hold two buffers.
     const size_t per_shift = ((size_t)1 << P.nf) * (dbl ? 16 : 8);
-    int64_t b = o.batch > 0 ? o.batch : (int64_t)(((P.pipe ? 64ull : 128ull) << 20) / per_shift);
+    const size_t xb = P.pipe ? (64ull << 20) : dbl ? (128ull << 20) : (256ull << 20);
+    int64_t b = o.batch > 0 ? o.batch : (int64_t)(xb / per_shift);
     if ((size_t)b * per_shift > (3ull << 30)) b = (int64_t)((3ull << 30) / per_shift);  // 32-bit offsets
     if (b < 1) b = 1;
     if (b > ((int64_t)1 << N)) b = (int64_t)1 << N;

@@ -376,13 +376,13 @@ static int launch_resident(int NL, RowPassArgs A, bool q2, hipStream_t st) {
 }
 
 // Two-pass row pass: rows of 2^NL values, tiles of 2^12 values (2^13 for NL = 13), RB register bits.
-template <typename T, int RB>
+template <typename T, int RB, bool SPLIT>
 static int launch_rowwrite_rb(int NL, RowPassArgs A, hipStream_t st) {
   constexpr int NT12 = 1 << (12 - RB), NT13 = 1 << (13 - RB);
 #define HM_RW(nl, nt)                                               \
   case nl:                                                          \
     A.n_tiles = row_tiles<nt, RB, nl>(A);                           \
-    launch_row_q<T, nt, RB, nl, true>(A, false, st);                \
+    launch_row_q<T, nt, RB, nl, true, SPLIT>(A, false, st);         \
     return OK;
   switch (NL) {
     HM_RW(6, NT12) HM_RW(7, NT12) HM_RW(8, NT12) HM_RW(9, NT12) HM_RW(10, NT12) HM_RW(11, NT12) HM_RW(12, NT12)
@@ -393,36 +393,37 @@ static int launch_rowwrite_rb(int NL, RowPassArgs A, hipStream_t st) {
   return fail(E_UNSUPPORTED, "row pass: no kernel for rows of 2^%d values (RB %d)", NL, RB);
 }
 
+// Split LDS staging is built for the default register tiles (2^5 FP32, 2^4 FP64) only.
 template <typename T>
-static int launch_rowwrite(int rb, int NL, RowPassArgs A, hipStream_t st) {
+static int launch_rowwrite(int rb, int NL, RowPassArgs A, bool split, hipStream_t st) {
   if constexpr (sizeof(T) == 4) {
-    if (rb == 5) return launch_rowwrite_rb<T, 5>(NL, A, st);
-    if (rb == 4) return launch_rowwrite_rb<T, 4>(NL, A, st);
+    if (rb == 5) return split ? launch_rowwrite_rb<T, 5, true>(NL, A, st) : launch_rowwrite_rb<T, 5, false>(NL, A, st);
+    if (rb == 4 && !split) return launch_rowwrite_rb<T, 4, false>(NL, A, st);
   } else {
-    if (rb == 4) return launch_rowwrite_rb<T, 4>(NL, A, st);
+    if (rb == 4) return split ? launch_rowwrite_rb<T, 4, true>(NL, A, st) : launch_rowwrite_rb<T, 4, false>(NL, A, st);
   }
-  return fail(E_UNSUPPORTED, "row pass: register tile 2^%d not built for this dtype", rb);
+  return fail(E_UNSUPPORTED, "row pass: register tile 2^%d (split %d) not built for this dtype", rb, (int)split);
 }
 
-template <typename T, int NT, int RB, int NH>
+template <typename T, int NT, int RB, int NH, bool SPLIT>
 static void launch_col_nh(ColPassArgs A, bool q2, hipStream_t st) {
   constexpr int CB = ilog2c(NT) + RB - NH;
   A.n_cb = (int64_t)1 << (A.nl - CB);
   A.n_tiles = A.n_slots * A.n_cb;
   const dim3 grid((unsigned)grid_for(A.n_tiles)), block(NT);
   ProfScope prof("sre_colpass", st);
-  if (q2) hipLaunchKernelGGL((k_sre_colpass<T, NT, RB, NH, CB, 2>), grid, block, 0, st, A);
-  else hipLaunchKernelGGL((k_sre_colpass<T, NT, RB, NH, CB, 0>), grid, block, 0, st, A);
+  if (q2) hipLaunchKernelGGL((k_sre_colpass<T, NT, RB, NH, CB, 2, SPLIT>), grid, block, 0, st, A);
+  else hipLaunchKernelGGL((k_sre_colpass<T, NT, RB, NH, CB, 0, SPLIT>), grid, block, 0, st, A);
 }
 
 // Column tiles of 2^col_tb values (col_tb - rb thread bits), RB register bits.
-template <typename T, int RB, int TBC>
+template <typename T, int RB, int TBC, bool SPLIT>
 static int launch_col_tb(int NH, ColPassArgs &A, bool q2, hipStream_t st) {
   constexpr int NT = 1 << (TBC - RB);
 #define HM_C(nh)                                                    \
   case nh:                                                          \
     if constexpr (nh >= RB && nh <= TBC) {                          \
-      launch_col_nh<T, NT, RB, nh>(A, q2, st);                      \
+      launch_col_nh<T, NT, RB, nh, SPLIT>(A, q2, st);               \
       return OK;                                                    \
     }                                                               \
     break;
@@ -432,20 +433,24 @@ static int launch_col_tb(int NH, ColPassArgs &A, bool q2, hipStream_t st) {
 }
 
 template <typename T>
-static int launch_colpass(int rb, int col_tb, int NH, ColPassArgs &A, bool q2, hipStream_t st) {
+static int launch_colpass(int rb, int col_tb, int NH, ColPassArgs &A, bool q2, bool split, hipStream_t st) {
   if (A.nl < col_tb - NH) return fail(E_UNSUPPORTED, "column pass: rows of 2^%d too short for 2^%d-row tiles", A.nl, NH);
   if constexpr (sizeof(T) == 4) {
-    if (rb == 5 && col_tb == 13) return launch_col_tb<T, 5, 13>(NH, A, q2, st);
-    if (rb == 5 && col_tb == 11) return launch_col_tb<T, 5, 11>(NH, A, q2, st);
-    if (rb == 4 && col_tb == 13) return launch_col_tb<T, 4, 13>(NH, A, q2, st);
-    if (rb == 4 && col_tb == 11) return launch_col_tb<T, 4, 11>(NH, A, q2, st);
+    if (rb == 5 && col_tb == 13)
+      return split ? launch_col_tb<T, 5, 13, true>(NH, A, q2, st) : launch_col_tb<T, 5, 13, false>(NH, A, q2, st);
+    if (rb == 5 && col_tb == 11)
+      return split ? launch_col_tb<T, 5, 11, true>(NH, A, q2, st) : launch_col_tb<T, 5, 11, false>(NH, A, q2, st);
+    if (rb == 4 && col_tb == 13 && !split) return launch_col_tb<T, 4, 13, false>(NH, A, q2, st);
+    if (rb == 4 && col_tb == 11 && !split) return launch_col_tb<T, 4, 11, false>(NH, A, q2, st);
   } else {
-    if (rb == 4 && col_tb == 12) return launch_col_tb<T, 4, 12>(NH, A, q2, st);
-    if (rb == 4 && col_tb == 10) return launch_col_tb<T, 4, 10>(NH, A, q2, st);
+    if (rb == 4 && col_tb == 12)
+      return split ? launch_col_tb<T, 4, 12, true>(NH, A, q2, st) : launch_col_tb<T, 4, 12, false>(NH, A, q2, st);
+    if (rb == 4 && col_tb == 10)
+      return split ? launch_col_tb<T, 4, 10, true>(NH, A, q2, st) : launch_col_tb<T, 4, 10, false>(NH, A, q2, st);
   }
-  return fail(E_UNSUPPORTED, "column pass: tile 2^%d with RB %d not built for this dtype", col_tb, rb);
+  return fail(E_UNSUPPORTED, "column pass: tile 2^%d with RB %d (split %d) not built for this dtype", col_tb, rb,
+              (int)split);
 }
-
 
 template <typename T>
 int shift_sums_t(const SrePlan &p, const void *psi, const QArgs &qa, uint64_t a0, const uint64_t *rows,
@@ -490,7 +495,7 @@ int shift_sums_t(const SrePlan &p, const void *psi, const QArgs &qa, uint64_t a0
     A.exch = exch;
     A.nacc = nacc;
     A.qa = qa;
-    int e = launch_rowwrite<T>(p.row_rb, p.nl, A, st);
+    int e = launch_rowwrite<T>(p.row_rb, p.nl, A, p.split != 0, st);
     if (e) return e;
     ColPassArgs C{};
     C.exch = exch;
@@ -505,7 +510,7 @@ int shift_sums_t(const SrePlan &p, const void *psi, const QArgs &qa, uint64_t a0
     C.prev_a0 = a0 + (uint64_t)prev_s0;
     C.prev_rows = rows ? rows + prev_s0 : nullptr;
     C.prev_shift_sums = shift_sums + prev_s0 * nacc;
-    e = launch_colpass<T>(p.col_rb, p.col_tb, p.nh, C, q2, st);
+    e = launch_colpass<T>(p.col_rb, p.col_tb, p.nh, C, q2, p.split != 0, st);
     if (e) return e;
     prev_s0 = s0;
     prev_nb = nb;

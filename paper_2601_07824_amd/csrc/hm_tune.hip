@@ -1,0 +1,152 @@
+// hm_tune.hip -- on-device autotuner for the qubit SRE plan.
+//
+// The two-pass kernels have several free choices (X-shifts per launch, LDS staging, sequential or
+// pipelined launches, the row/column split of the folded index bits), and which one is fastest
+// depends on n, the dtype and the memory level the exchange lands in.  The tuner times each
+// candidate plan on the caller's state over a prefix of the X-shifts (hipEvents on the caller's
+// stream), keeps the fastest in the handle, and planning on that handle then fills every option
+// the caller left automatic from that entry.
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <vector>
+
+#include "hm_internal.h"
+#include "hm_tile.h"
+
+namespace hm {
+
+PlanOpts plan_opts(const hm_context *h, int n, int dbl) {
+  PlanOpts o = h->opts;
+  for (const auto &t : h->tuned) {
+    if (t.n != n || t.dbl != dbl) continue;
+    if (!o.force_path) o.force_path = t.opts.force_path;
+    if (!o.batch) o.batch = t.opts.batch;
+    if (!o.row_rb) o.row_rb = t.opts.row_rb;
+    if (!o.col_rb) o.col_rb = t.opts.col_rb;
+    if (!o.row_bits) o.row_bits = t.opts.row_bits;
+    if (!o.pipeline) o.pipeline = t.opts.pipeline;
+    if (!o.lds_split) o.lds_split = t.opts.lds_split;
+    break;
+  }
+  return o;
+}
+
+// Candidate plans for (n, dbl): the workgroup-resident kernel when it applies, and two-pass plans
+// over exchange batches of 64/128/256 MiB x LDS staging x {sequential with the default split or
+// 11 or 12 row bits, pipelined}.  Options the caller fixed on the handle are kept.
+static std::vector<PlanOpts> candidates(const hm_context *h, int n, int dbl) {
+  std::vector<PlanOpts> c;
+  auto add = [&](PlanOpts o) {
+    // the caller's explicit choices win
+    const PlanOpts &u = h->opts;
+    if (u.force_path) o.force_path = u.force_path;
+    if (u.batch) o.batch = u.batch;
+    if (u.row_rb) o.row_rb = u.row_rb;
+    if (u.col_rb) o.col_rb = u.col_rb;
+    if (u.row_bits) o.row_bits = u.row_bits;
+    if (u.pipeline) o.pipeline = u.pipeline;
+    if (u.lds_split) o.lds_split = u.lds_split;
+    SrePlan p;
+    if (sre_plan(n, dbl, o, &p) != OK) return;
+    for (const auto &e : c)
+      if (!memcmp(&e, &o, sizeof(o))) return;
+    c.push_back(o);
+  };
+  PlanOpts r{};
+  r.force_path = 1;
+  add(r);
+  const int nf = n - 1;
+  const size_t per_shift = ((size_t)1 << nf) * (dbl ? 16 : 8);
+  int64_t last_b = -1;
+  for (int mib : {64, 128, 256}) {
+    int64_t b = (int64_t)(((size_t)mib << 20) / per_shift);
+    if (b < 1) b = 1;
+    if (b > ((int64_t)1 << n)) b = (int64_t)1 << n;
+    if (b == last_b) continue;
+    last_b = b;
+    for (int split : {1, 2})
+      for (int v = 0; v < 4; ++v) {
+        PlanOpts o{};
+        o.force_path = 2;
+        o.batch = b;
+        o.lds_split = split;
+        o.pipeline = v == 3 ? 2 : 1;
+        o.row_bits = v == 1 ? 12 : v == 2 ? 11 : 0;
+        add(o);
+      }
+  }
+  return c;
+}
+
+static int64_t tune_shifts(int n, int64_t sample) {
+  const int64_t all = (int64_t)1 << n;
+  if (sample <= 0) sample = 16384;
+  return sample < all ? sample : all;
+}
+
+size_t sre_autotune_workspace(const hm_context *h, int n, int dbl, int64_t sample) {
+  const int64_t k = tune_shifts(n, sample);
+  size_t need = 256;
+  for (const auto &o : candidates(h, n, dbl)) {
+    SrePlan p;
+    if (sre_plan(n, dbl, o, &p) != OK) continue;
+    const size_t b = sre_workspace(p, 1, k);
+    if (b > need) need = b;
+  }
+  return need;
+}
+
+int sre_autotune(hm_context *h, const void *psi, int n, int dbl, int64_t sample, void *ws, size_t ws_bytes,
+                 hipStream_t st, TunedPlan *best_out) {
+  const int64_t k = tune_shifts(n, sample);
+  QArgs qa{};
+  qa.nq = 1;
+  qa.q[0] = 2.0;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return fail(E_HIP, "autotune: hipEventCreate failed");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(E_HIP, "autotune: hipEventCreate failed");
+  }
+  TunedPlan best{};
+  best.ms_per_shift = -1.0;
+  int err = OK, tried = 0;
+  for (const auto &o : candidates(h, n, dbl)) {
+    SrePlan p;
+    if (sre_plan(n, dbl, o, &p) != OK) continue;
+    if (sre_workspace(p, 1, k) > ws_bytes) continue;
+    // warm-up run, then one timed run over the same k shifts
+    if ((err = sre_run(p, psi, qa, 0, nullptr, k, nullptr, nullptr, nullptr, ws, st)) != OK) break;
+    if (hipEventRecord(e0, st) != hipSuccess) { err = fail(E_HIP, "autotune: hipEventRecord failed"); break; }
+    if ((err = sre_run(p, psi, qa, 0, nullptr, k, nullptr, nullptr, nullptr, ws, st)) != OK) break;
+    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+      err = fail(E_HIP, "autotune: %s", hipGetErrorString(hipGetLastError()));
+      break;
+    }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    const double per = (double)ms / (double)k;
+    ++tried;
+    if (best.ms_per_shift < 0 || per < best.ms_per_shift) {
+      best.n = n;
+      best.dbl = dbl;
+      best.opts = o;
+      best.ms_per_shift = per;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err) return err;
+  if (!tried) return fail(E_WORKSPACE, "autotune: no candidate plan fits a workspace of %zu bytes", ws_bytes);
+  for (auto it = h->tuned.begin(); it != h->tuned.end(); ++it)
+    if (it->n == n && it->dbl == dbl) {
+      h->tuned.erase(it);
+      break;
+    }
+  h->tuned.push_back(best);
+  if (best_out) *best_out = best;
+  return OK;
+}
+
+}  // namespace hm

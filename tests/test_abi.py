@@ -184,6 +184,10 @@ def test_planner_accepts_every_configuration_the_gpu_tests_use():
             if pipe:
                 o += [(PIPE, 2), (SPLIT, pipe)]
             cases.append((o, n, dt))
+    for dt, n in ((1, 11), (1, 13), (0, 12), (0, 14)):
+        cases.append(([(FP, 2), (BS, 7), (SPLIT, 2)], n, dt))
+    for n in (16, 20):
+        cases += [([(PIPE, 1), (RB, 12 if n == 20 else 0), (SPLIT, 2)], n, 0), ([(PIPE, 1), (SPLIT, 2)], n, 1)]
     for dt, n in ((1, 13), (1, 14), (1, 15), (0, 14), (0, 15), (0, 16)):
         cases.append(([(FP, 1)], n, dt))
     cases += [([(FP, 2)], 16, 1), ([(FP, 2), (PIPE, 2)], 16, 1), ([(FP, 2), (PIPE, 2)], 16, 0)]
@@ -195,3 +199,15 @@ def test_planner_accepts_every_configuration_the_gpu_tests_use():
     for opts, n, dt in cases:
         st, msg = _ws_ok(opts, n, dt)
         assert st == HM_OK, (opts, n, dt, msg)
+
+
+def test_autotune_argument_errors(L, h):
+    good, ws = P(0x100000), P(0x200000)
+    b = ctypes.c_size_t()
+    assert L.hm_autotune_workspace(h, 20, 0, 4096, ctypes.byref(b)) == HM_OK and b.value >= 8 << 20
+    assert L.hm_autotune_workspace(h, 27, 0, 4096, ctypes.byref(b)) == HM_E_SIZE
+    assert L.hm_autotune(h, None, 12, 0, 0, ws, 1 << 30, None) == HM_E_ARG
+    assert L.hm_autotune(h, good, 12, 0, 0, P(0x200010), 1 << 30, None) == HM_E_ALIGN
+    v = (ctypes.c_int64 * 7)()
+    assert L.hm_tune_query(h, 12, 0, v, None) == HM_E_ARG  # nothing tuned yet
+    assert L.hm_tune_clear(h) == HM_OK

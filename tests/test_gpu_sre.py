@@ -110,6 +110,22 @@ def test_forced_two_pass(orc, hm, n, c64, rb):
         assert rel_err(got[:-1], want[:-1]) < TOL[c64], (got, want)
 
 
+@pytest.mark.parametrize("c64,n", [(False, 11), (False, 13), (True, 12), (True, 14)])
+def test_two_pass_split_lds(orc, hm, n, c64):
+    """Sequential two-pass kernels with split LDS staging (real and imaginary parts in turn)."""
+    ctx = hm.Context()
+    ctx.force_path(2)
+    ctx.batch_shifts(7)
+    ctx.set_option(hm.OPT_LDS_SPLIT, 2)
+    psi = S.brickwall_haar(n, 2 * n, seed=3040 + n)
+    x, w = gpu_state(psi, c64)
+    for q in ((2.0,), (1.0, 3.0)):
+        say(f"[sre two-pass split] n={n} c64={c64} q={q}")
+        got = hm.sre(x, q, ctx=ctx).cpu().numpy()
+        want = orc.sre_fwht(w, q)
+        assert rel_err(got[:-1], want[:-1]) < TOL[c64], (got, want)
+
+
 @pytest.mark.parametrize("split", [1, 2])
 @pytest.mark.parametrize("c64,n", [(False, 12), (False, 13), (False, 14), (True, 12), (True, 13), (True, 15)])
 def test_pipelined_two_pass(orc, hm, n, c64, split):
@@ -259,11 +275,15 @@ def test_full_size_sampled_rows(orc, hm, n):
     psi = S.brickwall_haar(n, 2 * n, seed=4100 + n)
     rows = np.concatenate([[0, 1, 2 ** n - 1], S.uniform_rows(n, 13, seed=4101)]).astype(np.int64)
     for c64, rb, rbits, pipe in ((True, 0, 0, 0), (False, 0, 0, 0), (True, 4, 0, 0), (True, 4, 12, 0), (True, 5, 9, 0),
-                                 (True, 0, 0, 1), (True, 0, 0, 2), (False, 0, 0, 2)):
+                                 (True, 0, 0, 1), (True, 0, 0, 2), (False, 0, 0, 2), (True, 0, 12, -2),
+                                 (False, 0, 0, -2)):
         ctx = hm.Context()
-        if pipe:
+        if pipe > 0:
             ctx.set_option(hm.OPT_PIPELINE, 2)
             ctx.set_option(hm.OPT_LDS_SPLIT, pipe)
+        elif pipe < 0:  # sequential launches, split LDS staging
+            ctx.set_option(hm.OPT_PIPELINE, 1)
+            ctx.set_option(hm.OPT_LDS_SPLIT, -pipe)
         if rb:
             ctx.set_option(hm.OPT_ROW_RB, rb)
             ctx.set_option(hm.OPT_COL_RB, rb)
@@ -294,3 +314,23 @@ def test_full_size_n16_vs_golden(hm):
             got = hm.sre(x, q, ctx=ctx).cpu().numpy()
             assert rel_err(got[:-1], want[:-1]) < (1e-5 if c64 else 1e-10), (got, want)
             assert abs(got[-1] - want[-1]) < (1e-5 if c64 else 1e-12)
+
+
+@pytest.mark.parametrize("c64,n", [(True, 16), (False, 14), (True, 18)])
+def test_autotuned_plan_matches(orc, hm, c64, n):
+    """The autotuner's choice is a valid plan and gives the same values as the default plan
+    (and as the oracle where it is quick)."""
+    psi = S.brickwall_haar(n, 2 * n, seed=3700 + n)
+    x, w = gpu_state(psi, c64)
+    ctx = hm.Context()
+    say(f"[autotune] n={n} c64={c64}")
+    plan = hm.autotune(x, 4096, ctx=ctx)
+    say(f"[autotune] plan {plan}")
+    assert plan["force_path"] in (1, 2) and plan["ms_per_shift"] > 0
+    got = hm.sre(x, (2.0,), ctx=ctx).cpu().numpy()
+    ref = hm.sre(x, (2.0,)).cpu().numpy()
+    assert rel_err(got[:-1], ref[:-1]) < (2e-6 if c64 else 1e-11), (got, ref)
+    assert abs(got[-1] - ref[-1]) < (1e-6 if c64 else 1e-12), (got, ref)
+    if n <= 14:
+        want = orc.sre_fwht(w, (2.0,))
+        assert rel_err(got[:-1], want[:-1]) < TOL[c64]
