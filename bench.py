@@ -48,7 +48,7 @@ def PROFILE_EVERY(N: int, shifts: int) -> int:
 HBM_PEAK_GBS = 8000.0
 
 
-def roofline(fam: str, N: int, vals_per_launch: float, t_launch: float, launches_per_step: int):
+def roofline(fam: str, N: int, vals_per_launch: float, t_launch: float, launches_per_step: int, plan: dict | None):
     """Roofline of one kernel family (complex64).  Two-pass kernels move the half-transformed vector
     through device memory (8 B per folded value written by the row pass and read by the column
     pass; the pipelined kernel does both): that compulsory exchange is their bound.  The
@@ -72,24 +72,32 @@ def roofline(fam: str, N: int, vals_per_launch: float, t_launch: float, launches
         achieved = bpl / t_launch / 1e9
         r.update({"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                   "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_launch": bpl,
-                  "traffic": traffic_for(fam, f"sre_n{N}_c64"), "valu": valu,
+                  "traffic": traffic_for(fam, f"sre_n{N}_c64", plan), "valu": valu,
                   "note": "achieved = exchange bytes (8 B per folded value per pass) / average launch time"})
     elif valu:
-        r.update({"bound": "alu", **valu, "traffic": traffic_for(fam, f"sre_n{N}_c64"),
+        r.update({"bound": "alu", **valu, "traffic": traffic_for(fam, f"sre_n{N}_c64", plan),
                   "note": "FP32 VALU without packed FP32: 39.3e12 lane-ops/s x flops per op of this kernel"})
     return r
 
 
-def traffic_for(kernel: str, workload: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if the kernel source is
-    unchanged since the counters were taken."""
+def traffic_for(kernel: str, workload: str, plan: dict | None):
+    """HBM/MALL bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE of the committed counter runs,
+    each scaled by what the same counter reads for a plain 256 MiB device copy), if the kernel
+    sources are unchanged since the counters were taken and the launch configuration is the same;
+    else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
-    if not os.path.exists(path):
+    if not os.path.exists(path) or not plan:
         return None
     try:
         rec = json.load(open(path)).get(f"{workload}/{kernel}")
-        src = open(os.path.join(ROOT, "paper_2601_07824_amd", "csrc", rec["source"]), "rb").read()
-        if hashlib.sha256(src).hexdigest()[:16] != rec["source_sha"]:
+        if rec is None:
+            return None
+        h = hashlib.sha256()
+        for src in rec["sources"]:
+            h.update(open(os.path.join(ROOT, src), "rb").read())
+        if h.hexdigest()[:16] != rec["source_sha"]:
+            return None
+        if any(plan.get(k) != v for k, v in rec["plan"].items()):
             return None
         return rec["bytes_per_launch"]
     except Exception:
@@ -182,6 +190,7 @@ def main():
     ap.add_argument("--batch", type=int, default=0, help="X-shifts per two-pass launch (0 = planner default)")
     ap.add_argument("--pipeline", type=int, default=0, choices=(0, 1, 2), help="HM_OPT_PIPELINE")
     ap.add_argument("--lds-split", type=int, default=0, choices=(0, 1, 2), help="HM_OPT_LDS_SPLIT")
+    ap.add_argument("--row-bits", type=int, default=0, help="HM_OPT_ROW_BITS (0 = planner default)")
     ap.add_argument("--no-autotune", action="store_true", help="skip the plan autotuner (untimed, before warm-up)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="counter calibration: time a plain device copy of this many MiB five times and exit")
@@ -220,9 +229,11 @@ def main():
         ctx.set_option(hm.OPT_PIPELINE, args.pipeline)
     if args.lds_split:
         ctx.set_option(hm.OPT_LDS_SPLIT, args.lds_split)
+    if args.row_bits:
+        ctx.set_option(hm.OPT_ROW_BITS, args.row_bits)
     shifts = args.shifts if args.shifts else 2 ** N
     plan = None
-    if not args.no_autotune and not (args.batch or args.pipeline or args.lds_split):
+    if not args.no_autotune and not (args.batch or args.pipeline or args.lds_split or args.row_bits):
         t = time.perf_counter()
         plan = hm.autotune(x, 16384, ctx=ctx)
         plan["tune_s"] = round(time.perf_counter() - t, 3)
@@ -259,7 +270,9 @@ def main():
     launches, timed, tot_ms = prof[fam]
     t_launch = tot_ms * 1e-3 / timed
     vals_per_launch = work / 2.0 * args.steps / launches  # folded values per launch
-    roof = roofline(fam, N, vals_per_launch, t_launch, launches // args.steps)
+    eff_plan = plan or {"batch_shifts": args.batch, "row_bits": args.row_bits, "lds_split": args.lds_split,
+                        "pipeline": args.pipeline}
+    roof = roofline(fam, N, vals_per_launch, t_launch, launches // args.steps, eff_plan)
 
     line = {
         "metric": "Pauli expectations/s for M_2 (N=20 qubits) & mana (N=12); fwd vs fwd+grad",
