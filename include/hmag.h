@@ -166,7 +166,10 @@ hm_status hm_sre_row_values(hm_handle h, const void *psi, int n, hm_dtype dtype,
 /* Fused forward + adjoint of M_q (q != 1): out = {M_q, lost_norm} (device, 2 doubles);
  * grad = dM_q/dRe(psi) + i dM_q/dIm(psi) (torch's convention), same dtype and length as psi
  * (device).  The adjoint differentiates chi_b(a) through Algorithm 2: with
- * w_b(a) = |chi_b(a)|^{2q-2} chi_b(a), dS_q/dpsi*_y = 2q sum_a psi_{y XOR a} [H^{(x)n} w(a)]_y. */
+ * w_b(a) = |chi_b(a)|^{2q-2} chi_b(a), dS_q/dpsi*_y = 2q sum_a psi_{y XOR a} [H^{(x)n} w(a)]_y.
+ * 1 <= n <= 20: one workgroup per X-shift up to n = 13 (HM_C64) / 12 (HM_C128), two-pass kernels
+ * above (and for n >= 12 when HM_OPT_FORCE_PATH is 2).  The transforms of each shift are recomputed
+ * (nothing is stored across shifts); the gradient accumulates in FP64. */
 hm_status hm_sre_grad(hm_handle h, const void *psi, int n, hm_dtype dtype, double q, double *out,
                       void *grad, void *ws, size_t ws_bytes, hipStream_t stream);
 

@@ -176,8 +176,8 @@ hm_status hm_workspace_size(hm_handle h, hm_op op, int n, hm_dtype dtype, int n_
       *bytes = sre_row_values_workspace(n, dbl);
       return HM_OK;
     case HM_OP_SRE_GRAD:
-      if (n < 1 || n > 24) return (hm_status)fail(E_SIZE, "gradient: n = %d outside [1, 24]", n);
-      *bytes = sre_grad_workspace(n, dbl);
+      if (n < 1 || n > 20) return (hm_status)fail(E_SIZE, "gradient: n = %d outside [1, 20]", n);
+      HM_TRY(sre_grad_workspace(plan_opts(h, n, dbl), n, dbl, bytes));
       return HM_OK;
     case HM_OP_SRE_SAMPLED: {
       if (count < 2) return (hm_status)fail(E_ARG, "sampled: count = %lld < 2", (long long)count);
@@ -278,13 +278,16 @@ hm_status hm_sre_grad(hm_handle h, const void *psi, int n, hm_dtype dtype, doubl
   g_err[0] = 0;
   if (!h) return (hm_status)fail(E_ARG, "h is NULL");
   HM_TRY(check_dtype(dtype));
-  if (n < 1 || n > 24) return (hm_status)fail(E_SIZE, "gradient: n = %d outside [1, 24]", n);
+  if (n < 1 || n > 20) return (hm_status)fail(E_SIZE, "gradient: n = %d outside [1, 20]", n);
   HM_TRY(check_ptr(psi, psi_align(dtype), "psi"));
   HM_TRY(check_ptr(grad, psi_align(dtype), "grad"));
   HM_TRY(check_ptr(out, 8, "out"));
   if (!(q > 0.0) || !isfinite(q) || q == 1.0) return (hm_status)fail(E_ARG, "gradient: q = %g must be positive, finite and != 1", q);
-  HM_TRY(check_ws(ws, ws_bytes, sre_grad_workspace(n, dtype == HM_C128)));
-  return (hm_status)sre_grad_launch(n, dtype == HM_C128, psi, q, out, grad, ws, ws_bytes, stream);
+  const PlanOpts o = plan_opts(h, n, dtype == HM_C128);
+  size_t need = 0;
+  HM_TRY(sre_grad_workspace(o, n, dtype == HM_C128, &need));
+  HM_TRY(check_ws(ws, ws_bytes, need));
+  return (hm_status)sre_grad_launch(o, n, dtype == HM_C128, psi, q, out, grad, ws, ws_bytes, stream);
 }
 
 // Workspace of a batched call: the largest need over its size classes.

@@ -35,13 +35,6 @@ struct GradArgs {
   double *spart;       // [gridDim][2]: sum |chi|^2, sum |chi|^{2q}
 };
 
-template <typename T, bool Q2>
-__device__ __forceinline__ T wfold(T x, T k, double q) {
-  // |k x|^{2q-2} x
-  if (Q2) return (k * k) * (x * x) * x;
-  const T ax = fabs(k * x);
-  return ax > T(0) ? (T)pow(ax, (T)(2.0 * q - 2.0)) * x : T(0);
-}
 
 // G index pair of register r (a != 0): x = x(c), y = x ^ a, c = tlo + (r << S0), resident path.
 template <int RB, int NL>
@@ -231,10 +224,41 @@ static int grad_blocks(int N) {
   return (int)(s < GRAD_MAX_BLOCKS ? s : GRAD_MAX_BLOCKS);
 }
 
-size_t sre_grad_workspace(int N, int dbl) {
-  if (N < 1 || N > grad_max_n(dbl)) return 256;
+static size_t grad1_workspace(int N, int dbl) {
   const size_t nb = (size_t)grad_blocks(N);
   return align256(nb * ((size_t)1 << N) * (dbl ? 16 : 8)) + align256(nb * 2 * sizeof(double)) + 256;
+}
+
+// Two-pass plan of the gradient: default split and tiles, sequential launches.
+static int grad2_plan(const PlanOpts &o, int N, int dbl, SrePlan *p) {
+  PlanOpts g{};
+  g.force_path = 2;
+  g.pipeline = 1;
+  g.batch = o.batch;
+  int e = sre_plan(N, dbl, g, p);
+  if (e) return e;
+  if (p->nf < 11 || p->nf > 19) return fail(E_UNSUPPORTED, "gradient: two-pass kernels cover n in [12, 20] (n = %d)", N);
+  return OK;
+}
+
+static bool grad_two_pass(const PlanOpts &o, int N, int dbl) { return N > grad_max_n(dbl) || (o.force_path == 2 && N >= 12); }
+
+int sre_grad_workspace(const PlanOpts &o, int N, int dbl, size_t *bytes) {
+  if (!grad_two_pass(o, N, dbl)) {
+    *bytes = grad1_workspace(N, dbl);
+    return OK;
+  }
+  SrePlan p;
+  int e = grad2_plan(o, N, dbl, &p);
+  if (e) return e;
+  *bytes = dbl ? sre_grad2_workspace_f64(p) : sre_grad2_workspace_f32(p);
+  return OK;
+}
+
+int grad_totals_launch(const double *shift_sums, int64_t n_shifts, int N, double q, double *out, double *scale,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_grad_totals, dim3(1), dim3(256), 0, st, shift_sums, (int)n_shifts, N, q, out, scale);
+  return hipPeekAtLastError() == hipSuccess ? OK : fail(E_HIP, "gradient totals: %s", hipGetErrorString(hipGetLastError()));
 }
 
 template <typename T, int RB, int NL>
@@ -283,10 +307,17 @@ static int grad_t(int N, const void *psi, double q, double *out, void *grad, voi
   return hipPeekAtLastError() == hipSuccess ? OK : fail(E_HIP, "gradient launch: %s", hipGetErrorString(hipGetLastError()));
 }
 
-int sre_grad_launch(int N, int dbl, const void *psi, double q, double *out, void *grad, void *ws, size_t ws_bytes,
-                    hipStream_t st) {
-  if (N > grad_max_n(dbl)) return fail(E_UNSUPPORTED, "gradient: n = %d above %d for this dtype", N, grad_max_n(dbl));
-  if (ws_bytes < sre_grad_workspace(N, dbl)) return fail(E_WORKSPACE, "gradient workspace too small");
+int sre_grad_launch(const PlanOpts &o, int N, int dbl, const void *psi, double q, double *out, void *grad, void *ws,
+                    size_t ws_bytes, hipStream_t st) {
+  size_t need = 0;
+  int e = sre_grad_workspace(o, N, dbl, &need);
+  if (e) return e;
+  if (ws_bytes < need) return fail(E_WORKSPACE, "gradient workspace of %zu bytes, %zu needed", ws_bytes, need);
+  if (grad_two_pass(o, N, dbl)) {
+    SrePlan p;
+    if ((e = grad2_plan(o, N, dbl, &p))) return e;
+    return dbl ? sre_grad2_f64(p, psi, q, out, grad, ws, st) : sre_grad2_f32(p, psi, q, out, grad, ws, st);
+  }
   return dbl ? grad_t<double>(N, psi, q, out, grad, ws, st) : grad_t<float>(N, psi, q, out, grad, ws, st);
 }
 

@@ -1,0 +1,328 @@
+// hm_grad2_kern.h -- two-pass fused forward + adjoint of M_q for states too large for one
+// workgroup (the gradient formulas are those of hm_grad.hip).  Per batch of X-shifts:
+//   1. row pass (forward, as for M_q): product and the row stages, into the exchange buffer;
+//   2. column pass with ADJ: the column stages, the sums of |chi|^2 and |chi|^{2q}, the adjoint
+//      seed |k U|^{2q-2} U, the column stages again in reverse order, written back in place;
+//   3. backward row pass: the row stages in reverse order, leaving Z = H^{(x)(N-1)} w in natural
+//      folded order (in place);
+//   4. accumulation: each workgroup owns a block of y and a group of the batch's shifts and adds
+//      2q psi_{y^a} [Z or conj Z]_{c(y)} (the unfolded form of the folded update) in registers,
+//      then into its own FP64 partial of G; no two workgroups write the same partial element, so
+//      no atomics are needed and the result is deterministic.
+// After the last batch, a fixed-order sum over the groups' partials, times 2 / ((1-q) S_q ln 2),
+// gives the gradient.
+#pragma once
+#include "hm_sre_kern.h"
+
+namespace hm {
+namespace {
+
+// Adjoint column pass (step 2), with the per-shift reduction of the previous batch's partials.
+template <typename T, int NT, int RB, int NH, int CB, int QM, bool SPLIT>
+__global__ __launch_bounds__(NT) void k_sre_colpass_adj(ColPassArgs A) {
+  using Sh = ColShape<T, NT, RB, NH, CB, SPLIT>;
+  __shared__ typename Sh::Elem lds[Sh::LDS_N];
+  __shared__ double red[NT / 64 + 1];
+  for (int64_t s = (int64_t)blockIdx.x * NT + threadIdx.x; s < A.prev_n_slots; s += (int64_t)gridDim.x * NT)
+    reduce_shift(A.prev_partials, s, A.n_cb, A.nacc, A.prev_a0, A.prev_rows, A.nf, A.qa, A.prev_shift_sums);
+  colpass_tiles<T, NT, RB, NH, CB, QM, SPLIT, true>(A, blockIdx.x, gridDim.x, lds, red);
+}
+
+// Backward row pass: rows of 2^NL adjoint values, read in the row pass's output layout (register
+// r of thread tlo holds row position r | (tlo << RB) at column (r << S0) | tlo), stages in reverse
+// round order, written back in natural order (position tlo + (r << S0)).
+template <typename T, int NT, int RB, int NL, bool SPLIT>
+__global__ __launch_bounds__(NT) void k_sre_rowback(RowPassArgs A) {
+  using Sh = RowShape<T, NT, RB, NL, SPLIT>;
+  __shared__ typename Sh::Elem lds[Sh::LDS_N];
+  constexpr int R = 1 << RB;
+  constexpr int LT = ilog2c(NT);
+  constexpr int TB = LT + RB;
+  static_assert(TB >= NL && NL >= RB, "tile must hold whole rows");
+  constexpr int S0 = NL - RB;
+  constexpr int K = (NL + RB - 1) / RB;
+  static_assert(K >= 2 && K <= 4, "two to four rounds");
+  constexpr int SEG = 1 << S0;
+  constexpr int G = 1 << (TB - NL);
+  vec2<T> *__restrict__ ex = (vec2<T> *)A.exch;
+  const uint32_t tau = threadIdx.x;
+  const uint32_t tlo = tau & (SEG - 1);
+  const uint32_t g = tau >> S0;
+  for (int64_t tile = blockIdx.x; tile < A.n_tiles; tile += gridDim.x) {
+    const int64_t rt = tile * G + g;
+    const bool active = (rt >> A.nh) < A.n_slots;
+    const uint32_t ob = ((uint32_t)rt << NL) | tlo;
+    T re[R], im[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      vec2<T> v{T(0), T(0)};
+      if (active) v = ld32(ex, ob + ((uint32_t)r << S0));
+      re[r] = v.x;
+      im[r] = v.y;
+    }
+    if constexpr (K >= 4) {
+      wht_regs<T, R, 0, rp_H(NL, RB, 3)>(re, im);
+      if constexpr (SPLIT) relayout_split<T, R, RB, rp_S(NL, RB, 3), rp_S(NL, RB, 2)>(re, im, lds, tau);
+      else relayout<T, R, RB, rp_S(NL, RB, 3), rp_S(NL, RB, 2)>(re, im, lds, tau);
+    }
+    if constexpr (K >= 3) {
+      wht_regs<T, R, 0, rp_H(NL, RB, 2)>(re, im);
+      if constexpr (SPLIT) relayout_split<T, R, RB, rp_S(NL, RB, 2), rp_S(NL, RB, 1)>(re, im, lds, tau);
+      else relayout<T, R, RB, rp_S(NL, RB, 2), rp_S(NL, RB, 1)>(re, im, lds, tau);
+    }
+    wht_regs<T, R, 0, rp_H(NL, RB, 1)>(re, im);
+    if constexpr (SPLIT) relayout_split<T, R, RB, rp_S(NL, RB, 1), rp_S(NL, RB, 0)>(re, im, lds, tau);
+    else relayout<T, R, RB, rp_S(NL, RB, 1), rp_S(NL, RB, 0)>(re, im, lds, tau);
+    wht_regs<T, R, 0, rp_H(NL, RB, 0)>(re, im);
+    if (active) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        vec2<T> v;
+        v.x = re[r];
+        v.y = im[r];
+        st32(ex, ob + ((uint32_t)r << S0), v);
+      }
+    }
+  }
+}
+
+struct AccumArgs {
+  const void *psi;
+  const void *z;       // [n_slots][2^nf] adjoint values in natural folded order
+  int nf;
+  int64_t n_slots;
+  uint64_t a0;
+  double q;
+  double2 *gpart;      // [groups][2^N]
+  int groups;
+  int64_t y_tiles;
+};
+
+// Gradient accumulation: block b -> y-tile b % y_tiles, shift group b / y_tiles; thread tau holds
+// y = tile * (256 * V) + v * 256 + tau for v < V.
+template <typename T, int V>
+__global__ __launch_bounds__(256) void k_grad_accum(AccumArgs A) {
+  const vec2<T> *__restrict__ psi = (const vec2<T> *)A.psi;
+  const int64_t tile = (int64_t)blockIdx.x % A.y_tiles;
+  const int grp = (int)((int64_t)blockIdx.x / A.y_tiles);
+  const int64_t per = (A.n_slots + A.groups - 1) / A.groups;
+  const int64_t s_lo = (int64_t)grp * per;
+  const int64_t s_hi = (s_lo + per) < A.n_slots ? (s_lo + per) : A.n_slots;
+  const uint32_t half = 1u << A.nf;
+  const T q2 = (T)(2.0 * A.q), q4 = (T)(4.0 * A.q);
+  uint32_t y[V];
+  T gr[V], gi[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    y[v] = (uint32_t)(tile * (256 * V)) + (uint32_t)(v * 256) + threadIdx.x;
+    gr[v] = gi[v] = T(0);
+  }
+  for (int64_t s = s_lo; s < s_hi; ++s) {
+    const uint64_t a = A.a0 + (uint64_t)s;
+    const vec2<T> *__restrict__ z = (const vec2<T> *)A.z + ((size_t)s << A.nf);
+    if (a == 0) {
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const uint32_t c = y[v] & (half - 1u);
+        const vec2<T> zc = ld32(z, c);
+        const vec2<T> p = ld32(psi, y[v]);
+        const T f = q2 * ((y[v] & half) ? (zc.x - zc.y) : (zc.x + zc.y));
+        gr[v] = fmaT(f, p.x, gr[v]);
+        gi[v] = fmaT(f, p.y, gi[v]);
+      }
+    } else {
+      const int j = 63 - __builtin_clzll(a);
+      const uint32_t lomask = (1u << j) - 1u;
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const uint32_t yj = (y[v] >> j) & 1u;
+        const uint32_t x = yj ? (y[v] ^ (uint32_t)a) : y[v];
+        const uint32_t c = (x & lomask) | ((x >> (j + 1)) << j);
+        vec2<T> zc = ld32(z, c);
+        if (yj) zc.y = -zc.y;
+        const vec2<T> p = ld32(psi, y[v] ^ (uint32_t)a);
+        // G_y += 4q psi_{y^a} zc
+        gr[v] = fmaT(q4, fmaT(p.x, zc.x, -(p.y * zc.y)), gr[v]);
+        gi[v] = fmaT(q4, fmaT(p.x, zc.y, p.y * zc.x), gi[v]);
+      }
+    }
+  }
+  if (s_lo >= s_hi) return;
+  double2 *gp = A.gpart + ((size_t)grp << (A.nf + 1));
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    double2 o = gp[y[v]];
+    o.x += (double)gr[v];
+    o.y += (double)gi[v];
+    gp[y[v]] = o;
+  }
+}
+
+template <typename T>
+__global__ void k_grad2_final(const double2 *gpart, int groups, int64_t n, const double *scale, vec2<T> *grad) {
+  const int64_t y = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (y >= n) return;
+  double gr = 0.0, gi = 0.0;
+  for (int g = 0; g < groups; ++g) {
+    const double2 v = gpart[(size_t)g * n + y];
+    gr += v.x;
+    gi += v.y;
+  }
+  vec2<T> o;
+  o.x = (T)(scale[0] * gr);
+  o.y = (T)(scale[0] * gi);
+  grad[y] = o;
+}
+
+__global__ void k_zero2(double2 *p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = double2{0.0, 0.0};
+}
+
+// ---- launchers (default two-pass split only) -----------------------------------------------------
+template <typename T, int RB, int NF, bool SPLIT>
+static void grad2_launch_nf(int step, RowPassArgs &A, ColPassArgs &C, bool q2, hipStream_t st) {
+  constexpr int TB = sre_default_col_tb(NF, sizeof(T) == 8, RB);
+  constexpr int NL = sre_default_nl(NF, TB, RB);
+  constexpr int NH = NF - NL;
+  constexpr int CB = TB - NH;
+  // The adjoint column pass keeps its loads' addresses for the write-back: 2^4 values per thread
+  // keep it within the register file at two waves per SIMD.
+  constexpr int RBC = 4;
+  constexpr int NTC = 1 << (TB - RBC);
+  if (step == 2) {
+    C.n_cb = (int64_t)1 << (C.nl - CB);
+    C.n_tiles = C.n_slots * C.n_cb;
+    const dim3 grid((unsigned)grid_for(C.n_tiles)), block(NTC);
+    ProfScope prof("sre_grad_colpass", st);
+    if (q2) hipLaunchKernelGGL((k_sre_colpass_adj<T, NTC, RBC, NH, CB, 2, SPLIT>), grid, block, 0, st, C);
+    else hipLaunchKernelGGL((k_sre_colpass_adj<T, NTC, RBC, NH, CB, 0, SPLIT>), grid, block, 0, st, C);
+  } else {
+    constexpr int TBR = NL > 12 ? 13 : 12;
+    constexpr int NTR = 1 << (TBR - RB);
+    A.n_tiles = row_tiles<NTR, RB, NL>(A);
+    const dim3 grid((unsigned)grid_for(A.n_tiles)), block(NTR);
+    ProfScope prof("sre_grad_rowback", st);
+    hipLaunchKernelGGL((k_sre_rowback<T, NTR, RB, NL, SPLIT>), grid, block, 0, st, A);
+  }
+}
+
+template <typename T, bool SPLIT>
+static int grad2_launch(int nf, int step, RowPassArgs &A, ColPassArgs &C, bool q2, hipStream_t st) {
+  constexpr int RB = ResidentRB<T>::value;
+#define HM_G2(nf_)                                                  \
+  case nf_:                                                         \
+    grad2_launch_nf<T, RB, nf_, SPLIT>(step, A, C, q2, st);         \
+    return OK;
+  switch (nf) {
+    HM_G2(11) HM_G2(12) HM_G2(13) HM_G2(14) HM_G2(15) HM_G2(16) HM_G2(17) HM_G2(18) HM_G2(19)
+    default: break;
+  }
+#undef HM_G2
+  return fail(E_UNSUPPORTED, "two-pass gradient: no kernels for 2^%d folded values", nf);
+}
+
+static inline int grad2_groups(int N) {
+  const int64_t tiles = ((int64_t)1 << N) / 1024;
+  int64_t g = 2048 / (tiles > 0 ? tiles : 1);
+  return (int)(g < 1 ? 1 : g > 256 ? 256 : g);
+}
+
+static inline size_t grad2_workspace(const SrePlan &p) {
+  const size_t n = (size_t)1 << p.N;
+  return align256(n * 2 * sizeof(double)) + sre_exch_bytes(p) +
+         2 * align256((size_t)p.batch * (size_t)sre_col_blocks(p) * 2 * sizeof(double)) +
+         align256((size_t)grad2_groups(p.N) * n * sizeof(double2)) + 256;
+}
+
+template <typename T>
+int grad2_t(const SrePlan &p, const void *psi, double q, double *out, void *grad, char *w, hipStream_t st) {
+  const int N = p.N, nf = p.nf;
+  const int64_t n_shifts = (int64_t)1 << N;
+  QArgs qa{};
+  qa.nq = 1;
+  qa.q[0] = q;
+  const bool q2 = q == 2.0;
+  const int nacc = 2;
+  const int groups = grad2_groups(N);
+  const int64_t n_cb = sre_col_blocks(p);
+  // workspace: [shift sums][exchange][partials x 2][G partials][scale]
+  double *shift_sums = (double *)w;
+  w += align256((size_t)n_shifts * nacc * sizeof(double));
+  void *exch = w;
+  w += sre_exch_bytes(p);
+  const size_t pbytes = align256((size_t)p.batch * (size_t)n_cb * nacc * sizeof(double));
+  double *partials[2] = {(double *)w, (double *)(w + pbytes)};
+  w += 2 * pbytes;
+  double2 *gpart = (double2 *)w;
+  w += align256((size_t)groups * (size_t)n_shifts * sizeof(double2));
+  double *scale = (double *)w;
+  {
+    const int64_t n = (int64_t)groups * n_shifts;
+    hipLaunchKernelGGL(k_zero2, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, gpart, n);
+  }
+  int64_t prev_s0 = 0, prev_nb = 0;
+  int k = 0;
+  for (int64_t s0 = 0; s0 < n_shifts; s0 += p.batch, ++k) {
+    const int64_t nb = (n_shifts - s0) < p.batch ? (n_shifts - s0) : p.batch;
+    RowPassArgs A{};
+    A.psi = psi;
+    A.nf = nf;
+    A.nh = p.nh;
+    A.n_slots = nb;
+    A.a0 = (uint64_t)s0;
+    A.exch = exch;
+    A.nacc = nacc;
+    A.qa = qa;
+    int e = launch_rowwrite<T>(p.row_rb, p.nl, A, p.split != 0, st);
+    if (e) return e;
+    ColPassArgs C{};
+    C.exch = exch;
+    C.nl = p.nl;
+    C.n_slots = nb;
+    C.partials = partials[k & 1];
+    C.nacc = nacc;
+    C.qa = qa;
+    C.nf = nf;
+    C.a0 = (uint64_t)s0;
+    C.prev_partials = partials[(k + 1) & 1];
+    C.prev_n_slots = prev_nb;
+    C.prev_a0 = (uint64_t)prev_s0;
+    C.prev_shift_sums = shift_sums + prev_s0 * nacc;
+    e = p.split ? grad2_launch<T, true>(nf, 2, A, C, q2, st) : grad2_launch<T, false>(nf, 2, A, C, q2, st);
+    if (e) return e;
+    e = p.split ? grad2_launch<T, true>(nf, 3, A, C, q2, st) : grad2_launch<T, false>(nf, 3, A, C, q2, st);
+    if (e) return e;
+    AccumArgs G{};
+    G.psi = psi;
+    G.z = exch;
+    G.nf = nf;
+    G.n_slots = nb;
+    G.a0 = (uint64_t)s0;
+    G.q = q;
+    G.gpart = gpart;
+    G.groups = groups;
+    G.y_tiles = n_shifts / 1024;
+    {
+      ProfScope prof("sre_grad_accum", st);
+      hipLaunchKernelGGL((k_grad_accum<T, 4>), dim3((unsigned)(G.y_tiles * groups)), dim3(256), 0, st, G);
+    }
+    prev_s0 = s0;
+    prev_nb = nb;
+  }
+  {
+    const int thr = 128;
+    hipLaunchKernelGGL(k_sre_shift_reduce, dim3((unsigned)((prev_nb + thr - 1) / thr)), dim3(thr), 0, st,
+                       partials[(k + 1) & 1], prev_nb, n_cb, nacc, (uint64_t)prev_s0, nullptr, nf, qa,
+                       shift_sums + prev_s0 * nacc);
+  }
+  int e = grad_totals_launch(shift_sums, n_shifts, N, q, out, scale, st);
+  if (e) return e;
+  hipLaunchKernelGGL(k_grad2_final<T>, dim3((unsigned)((n_shifts + 255) / 256)), dim3(256), 0, st,
+                     (const double2 *)gpart, groups, n_shifts, (const double *)scale, (vec2<T> *)grad);
+  return hipPeekAtLastError() == hipSuccess ? OK
+                                            : fail(E_HIP, "two-pass gradient launch: %s", hipGetErrorString(hipGetLastError()));
+}
+
+}  // namespace
+}  // namespace hm

@@ -157,9 +157,17 @@ int sre_row_values_launch(int N, int dbl, const void *psi, uint64_t a, double *o
 size_t sre_row_values_workspace(int N, int dbl);
 
 // ---- SRE gradient ----------------------------------------------------------------------------
-int sre_grad_launch(int N, int dbl, const void *psi, double q, double *out, void *grad, void *ws, size_t ws_bytes,
-                    hipStream_t stream);
-size_t sre_grad_workspace(int N, int dbl);
+// Workgroup-resident kernel up to n = 13 (FP32) / 12 (FP64), two-pass kernels (default split)
+// for n in [12, 20]; opts.force_path = 2 selects the two-pass kernels where both exist.
+int sre_grad_launch(const PlanOpts &opts, int N, int dbl, const void *psi, double q, double *out, void *grad,
+                    void *ws, size_t ws_bytes, hipStream_t stream);
+int sre_grad_workspace(const PlanOpts &opts, int N, int dbl, size_t *bytes);
+int grad_totals_launch(const double *shift_sums, int64_t n_shifts, int N, double q, double *out, double *scale,
+                       hipStream_t stream);
+int sre_grad2_f32(const SrePlan &p, const void *psi, double q, double *out, void *grad, void *ws, hipStream_t st);
+int sre_grad2_f64(const SrePlan &p, const void *psi, double q, double *out, void *grad, void *ws, hipStream_t st);
+size_t sre_grad2_workspace_f32(const SrePlan &p);
+size_t sre_grad2_workspace_f64(const SrePlan &p);
 
 // ---- Mana ------------------------------------------------------------------------------------
 int mana_launch(int N, int dbl, const void *psi, uint64_t a0, uint64_t a1, double *sums, double *out, void *ws,

@@ -104,4 +104,12 @@ __device__ __forceinline__ void sre_product(const vec2<T> *__restrict__ psi, uin
 
 }
 
+// Adjoint seed of one folded real value: |k x|^{2q-2} x (k = 2 for a != 0, 1 for a = 0).
+template <typename T, bool Q2>
+__device__ __forceinline__ T wfold(T x, T k, double q) {
+  if (Q2) return (k * k) * (x * x) * x;
+  const T ax = fabs(k * x);
+  return ax > T(0) ? (T)pow(ax, (T)(2.0 * q - 2.0)) * x : T(0);
+}
+
 }  // namespace hm

@@ -196,6 +196,7 @@ struct ColPassArgs {
   const uint64_t *prev_rows;
   double *prev_shift_sums;
   int nf;
+  uint64_t a0;  // shift of slot 0 (adjoint column pass only)
 };
 
 // Per-shift sum over column blocks (fixed order), unfolded and scaled.
@@ -231,7 +232,10 @@ struct ColShape {
 
 // Column tiles t0, t0 + tstep, ... < A.n_tiles (the previous batch's per-shift reduction is done by
 // the caller).
-template <typename T, int NT, int RB, int NH, int CB, int QM, bool SPLIT>
+// ADJ (gradient): after the sums, each value is replaced by its adjoint seed |k U|^{2q-2} U, the
+// column stages run again in reverse order (the transform is its own adjoint) and the tile is
+// written back in place.
+template <typename T, int NT, int RB, int NH, int CB, int QM, bool SPLIT, bool ADJ = false>
 __device__ __forceinline__ void colpass_tiles(const ColPassArgs &A, int64_t t0, int64_t tstep,
                                               typename ColShape<T, NT, RB, NH, CB, SPLIT>::Elem *lds, double *red) {
   constexpr int R = 1 << RB;
@@ -289,6 +293,40 @@ __device__ __forceinline__ void colpass_tiles(const ColPassArgs &A, int64_t t0, 
     if (tau == 0) {
       double *o = A.partials + (slot * A.n_cb + cb) * A.nacc;
       for (int k = 0; k < A.nacc; ++k) o[k] = s[k];
+    }
+    if constexpr (ADJ) {
+      const T kf = (A.a0 + (uint64_t)slot == 0) ? T(1) : T(2);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        re[r] = wfold<T, QM == 2>(re[r], kf, A.qa.q[0]);
+        im[r] = wfold<T, QM == 2>(im[r], kf, A.qa.q[0]);
+      }
+      if constexpr (K >= 4) {
+        wht_regs<T, R, cp_L(NH, RB, CB, 3), cp_H(NH, RB, CB, 3)>(re, im);
+        if constexpr (SPLIT) relayout_split<T, R, RB, cp_S(NH, RB, CB, 3), cp_S(NH, RB, CB, 2)>(re, im, lds, tau);
+        else relayout<T, R, RB, cp_S(NH, RB, CB, 3), cp_S(NH, RB, CB, 2)>(re, im, lds, tau);
+      }
+      if constexpr (K >= 3) {
+        wht_regs<T, R, cp_L(NH, RB, CB, 2), cp_H(NH, RB, CB, 2)>(re, im);
+        if constexpr (SPLIT) relayout_split<T, R, RB, cp_S(NH, RB, CB, 2), cp_S(NH, RB, CB, 1)>(re, im, lds, tau);
+        else relayout<T, R, RB, cp_S(NH, RB, CB, 2), cp_S(NH, RB, CB, 1)>(re, im, lds, tau);
+      }
+      if constexpr (K >= 2) {
+        wht_regs<T, R, cp_L(NH, RB, CB, 1), cp_H(NH, RB, CB, 1)>(re, im);
+        if constexpr (SPLIT) relayout_split<T, R, RB, cp_S(NH, RB, CB, 1), cp_S(NH, RB, CB, 0)>(re, im, lds, tau);
+        else relayout<T, R, RB, cp_S(NH, RB, CB, 1), cp_S(NH, RB, CB, 0)>(re, im, lds, tau);
+      }
+      wht_regs<T, R, cp_L(NH, RB, CB, 0), cp_H(NH, RB, CB, 0)>(re, im);
+      vec2<T> *exw = (vec2<T> *)A.exch;
+      const uint32_t base = ((uint32_t)slot << (NH + A.nl)) + ((uint32_t)cb << CB) + col;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const uint32_t row = (uint32_t)r | (rowhi << RB);
+        vec2<T> v;
+        v.x = re[r];
+        v.y = im[r];
+        st32(exw, base + (row << A.nl), v);
+      }
     }
   }
 }

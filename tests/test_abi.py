@@ -211,3 +211,20 @@ def test_autotune_argument_errors(L, h):
     v = (ctypes.c_int64 * 7)()
     assert L.hm_tune_query(h, 12, 0, v, None) == HM_E_ARG  # nothing tuned yet
     assert L.hm_tune_clear(h) == HM_OK
+
+
+def test_gradient_workspace_all_sizes(L, h):
+    b = ctypes.c_size_t()
+    for dt in (0, 1):
+        for n in range(1, 21):
+            assert L.hm_workspace_size(h, 3, n, dt, 1, 0, ctypes.byref(b)) == HM_OK, (n, dt, L.hm_last_error())
+            assert b.value >= 256
+        assert L.hm_workspace_size(h, 3, 21, dt, 1, 0, ctypes.byref(b)) == HM_E_SIZE
+    hh = P()
+    assert L.hm_create(ctypes.byref(hh)) == HM_OK
+    try:
+        assert L.hm_set_option(hh, 1, 2) == HM_OK
+        for dt in (0, 1):
+            assert L.hm_workspace_size(hh, 3, 12, dt, 1, 0, ctypes.byref(b)) == HM_OK
+    finally:
+        L.hm_destroy(hh)

@@ -131,3 +131,94 @@ def test_grad_determinism(hm):
     a = hm.sre_grad(x, 2.0)[1].cpu().numpy()
     b = hm.sre_grad(x, 2.0)[1].cpu().numpy()
     assert np.array_equal(a, b)
+
+
+# ---- two-pass gradient (row pass, adjoint column pass, backward row pass, accumulation) ----------
+@pytest.mark.parametrize("c64,n,forced", [(False, 12, True), (True, 12, True), (True, 13, True), (False, 13, False),
+                                          (True, 14, False), (False, 14, False)])
+def test_grad_two_pass_vs_fwht_oracle(orc, hm, c64, n, forced):
+    psi = S.ry_rz_cz_state(n, np.random.default_rng(6600 + n).uniform(0, 2 * math.pi, (2, 2, n)))
+    x, w = gpu_state(psi, c64)
+    ctx = hm.Context()
+    if forced:
+        ctx.force_path(2)
+    ctx.batch_shifts(96)  # several batches, the last one ragged
+    for q in ((2.0, 3.0) if n <= 13 else (2.0,)):
+        say(f"[grad two-pass] n={n} c64={c64} forced={forced} q={q}")
+        out, g = hm.sre_grad(x, q, ctx=ctx)
+        want_out, want_g = orc.sre_grad_fwht(w, q)
+        err = rel_l2(g.cpu().numpy().astype(np.complex128), want_g)
+        assert err < (1e-4 if c64 else 1e-9), (n, q, err)
+        np.testing.assert_allclose(out.cpu().numpy(), want_out, rtol=(1e-5 if c64 else 1e-11),
+                                   atol=1e-6 if c64 else 1e-12)
+
+
+@pytest.mark.parametrize("n", [16, 18])
+def test_grad_two_pass_identities_and_dtypes(hm, n):
+    """Homogeneity Re<g, psi> = 4q / ((1-q) ln 2) and Im<g, psi> = 0 at full size, complex64 against
+    complex128 gradients, and M_q against the forward entry point."""
+    psi = S.ry_rz_cz_state(n, np.random.default_rng(6700 + n).uniform(0, 2 * math.pi, (2, 2, n)))
+    gs = {}
+    for c64 in (False, True):
+        x, _ = gpu_state(psi, c64)
+        say(f"[grad two-pass full] n={n} c64={c64}")
+        out, g = hm.sre_grad(x, 2.0)
+        gs[c64] = g.cpu().numpy().astype(np.complex128)
+        ip = np.vdot(gs[c64], x.cpu().numpy().astype(np.complex128))
+        want = 4 * 2.0 / ((1 - 2.0) * math.log(2))
+        tol = 1e-4 if c64 else 1e-9
+        assert abs(ip.real - want) < tol * abs(want) and abs(ip.imag) < tol * abs(want), ip
+        m = hm.sre(x, (2.0,)).cpu().numpy()
+        assert abs(out.cpu().numpy()[0] - m[0]) < (1e-5 if c64 else 1e-10) * max(1.0, abs(m[0]))
+    assert rel_l2(gs[True], gs[False]) < 1e-4
+
+
+def test_grad_two_pass_central_differences(hm):
+    """N = 16 (two-pass): h = 1e-6 central differences of the FP64 forward on sampled coordinates."""
+    n = 16
+    psi = S.gaussian_state(n, seed=6800)
+    x = torch.from_numpy(psi).to(_dev())
+    _, g = hm.sre_grad(x, 2.0)
+    g = g.cpu().numpy()
+    h = 1e-6
+    for y in np.random.default_rng(6801).choice(2 ** n, 8, replace=False):
+        for unit in (1.0, 1j):
+            e = np.zeros_like(psi)
+            e[y] = unit * h
+            mp = hm.sre(torch.from_numpy(psi + e).to(_dev()), (2.0,))[0].item()
+            mm = hm.sre(torch.from_numpy(psi - e).to(_dev()), (2.0,))[0].item()
+            fd = (mp - mm) / (2 * h)
+            an = g[y].real if unit == 1.0 else g[y].imag
+            say(f"[grad two-pass fd] y={y} unit={unit} fd={fd:.9e} an={an:.9e}")
+            assert abs(fd - an) < 1e-6 * max(1.0, abs(an)) + 1e-5 * abs(an), (y, unit, fd, an)
+
+
+def test_autograd_circuit_two_pass(hm):
+    """d M_2(psi(theta)) / d theta at N = 14 through torch.autograd and the two-pass adjoint, against
+    central differences of the complex128 forward on the angles."""
+    n = 14
+    dev = _dev()
+    ang0 = np.random.default_rng(6900).uniform(0, 2 * math.pi, (2, 2, n))
+    ang = torch.tensor(ang0, dtype=torch.float64, device=dev, requires_grad=True)
+    psi = S.ry_rz_cz_state_torch(n, ang)
+    say("[grad autograd] circuit n=14 two-pass")
+    m2 = hm.SRE.apply(psi, 2.0)
+    m2.backward()
+    got = ang.grad.cpu().numpy()
+    h = 1e-6
+    fd = np.zeros_like(ang0)
+    for idx in np.ndindex(ang0.shape):
+        ap, am = ang0.copy(), ang0.copy()
+        ap[idx] += h
+        am[idx] -= h
+        fp = hm.sre(torch.from_numpy(S.ry_rz_cz_state(n, ap)).to(dev), (2.0,))[0].item()
+        fm = hm.sre(torch.from_numpy(S.ry_rz_cz_state(n, am)).to(dev), (2.0,))[0].item()
+        fd[idx] = (fp - fm) / (2 * h)
+    assert np.max(np.abs(got - fd)) < 1e-6 * max(1.0, np.max(np.abs(fd))), np.max(np.abs(got - fd))
+
+
+def test_grad_two_pass_deterministic(hm):
+    x, _ = gpu_state(S.gaussian_state(15, seed=6950), True)
+    a = hm.sre_grad(x, 2.0)[1].cpu().numpy()
+    b = hm.sre_grad(x, 2.0)[1].cpu().numpy()
+    assert np.array_equal(a, b)
