@@ -133,14 +133,17 @@ def _timed(torch, fn, reps=1):
 
 def secondary(hm, S, torch, dev, psi, N):
     """The other rows of the metric, each timed once after a warm-up call (wall clock around the
-    call, state resident): complex128 forward at the headline N, mana at N = 12, fused
-    forward + adjoint against the plain forwards at N = 13 (workgroup-resident gradient), the
-    batched form on 1024 states of uneven size, and the Monte Carlo estimator at N = 24."""
+    call, state resident; plans autotuned where noted): complex128 forward at the headline N
+    (tuned), mana at N = 12, fused forward + adjoint against the plain forwards at N = 13
+    (workgroup-resident gradient) and N = 18 (two-pass gradient), the batched form on 1024 states
+    of uneven size, and the Monte Carlo estimator at N = 24 (tuned)."""
     import numpy as np
     sec = {}
     try:
         x128 = torch.from_numpy(psi).to(dev)
-        dt, o = _timed(torch, lambda: hm.sre(x128, (2.0,)))
+        c128 = hm.Context()
+        hm.autotune(x128, 16384, ctx=c128)
+        dt, o = _timed(torch, lambda: hm.sre(x128, (2.0,), ctx=c128))
         sec["sre_fwd_c128_n%d" % N] = {"value": 4.0 ** N / dt, "unit": "Pauli expectations/s", "ms": dt * 1e3,
                                         "M2": float(o[0].item())}
         del x128
@@ -157,6 +160,15 @@ def secondary(hm, S, torch, dev, psi, N):
                         ("sre_fwd_c128_n13", lambda: hm.sre(g128, (2.0,)))):
             dt, _ = _timed(torch, fn, reps=20)
             sec[key] = {"value": 4.0 ** ng / dt, "unit": "Pauli expectations/s", "ms": dt * 1e3}
+        ng = 18
+        pg = S.ry_rz_cz_state(ng, np.random.default_rng(4018).uniform(0, 2 * math.pi, (2, 2, ng)))
+        g64 = torch.from_numpy(S.to_c64_exact(pg)[0]).to(dev)
+        g128 = torch.from_numpy(pg).to(dev)
+        for key, fn in (("sre_fwd_grad_c64_n18", lambda: hm.sre_grad(g64, 2.0)),
+                        ("sre_fwd_c64_n18", lambda: hm.sre(g64, (2.0,))),
+                        ("sre_fwd_c128_n18", lambda: hm.sre(g128, (2.0,)))):
+            dt, _ = _timed(torch, fn)
+            sec[key] = {"value": 4.0 ** ng / dt, "unit": "Pauli expectations/s", "ms": dt * 1e3}
         rng = np.random.default_rng(5005)
         ns = rng.integers(10, 17, size=1024)
         states = [torch.from_numpy(S.to_c64_exact(S.gaussian_state(int(n), seed=5000 + i))[0]).to(dev)
@@ -168,7 +180,9 @@ def secondary(hm, S, torch, dev, psi, N):
         g = torch.Generator(device="cpu").manual_seed(2424)
         v = torch.view_as_complex(torch.randn(2 ** 24, 2, generator=g, dtype=torch.float32)).to(dev)
         v /= torch.linalg.vector_norm(v)
-        dt, o = _timed(torch, lambda: hm.sre_sampled(v, n_rows=4096, seed=24))
+        c24 = hm.Context()
+        hm.autotune(v, 256, ctx=c24)
+        dt, o = _timed(torch, lambda: hm.sre_sampled(v, n_rows=4096, seed=24, ctx=c24))
         sec["sre_mc_n24_4096rows_c64"] = {"value": 4097 * 2.0 ** 24 / dt, "unit": "Pauli expectations/s",
                                           "ms": dt * 1e3, "M2_hat": float(o[0].item()),
                                           "stderr": float(o[1].item())}

@@ -70,7 +70,7 @@ const char *hm_version(void);
 /* Options (testing and tuning); 0 always means "automatic".
  *   HM_OPT_FORCE_PATH: SRE kernel family, 1 = workgroup-resident (one workgroup holds a whole
  *     folded shift vector), 2 = two-pass (row pass, exchange through device memory, column pass).
- *   HM_OPT_BATCH_SHIFTS: X-shifts covered by one two-pass launch pair.
+ *   HM_OPT_BATCH_SHIFTS: X-shifts covered by one two-pass launch pair (qubit SRE and qutrit mana).
  *   HM_OPT_ROW_RB / HM_OPT_COL_RB: log2 of the values each thread holds in registers in the
  *     two-pass row / column kernels (4 or 5 for HM_C64, 4 for HM_C128).
  *   HM_OPT_ROW_BITS: index bits handled by the two-pass row pass (6..13); the column pass takes
@@ -96,7 +96,7 @@ hm_status hm_set_option(hm_handle h, hm_option opt, int64_t value);
 /* Autotuner.  Times every candidate SRE plan for (n, dtype) on the state psi (device) over the
  * first sample_shifts X-shifts (16384 if <= 0, at most 2^n): the workgroup-resident kernel where it
  * applies, and two-pass plans over exchange batches of 64/128/256 MiB, both LDS stagings,
- * sequential launches with the default, 11 or 12 row bits, and pipelined launches.  Options
+ * sequential launches with the default, 11, 12 or 13 row bits, and pipelined launches.  Options
  * already set on the handle are kept fixed.  The fastest plan is stored in the handle; later calls
  * on the handle for the same (n, dtype) fill every option left automatic from it.  Candidates
  * whose workspace exceeds ws_bytes are skipped (hm_autotune_workspace gives the size that admits

@@ -25,7 +25,7 @@ __global__ __launch_bounds__(NT) void k_sre_colpass_adj(ColPassArgs A) {
   __shared__ double red[NT / 64 + 1];
   for (int64_t s = (int64_t)blockIdx.x * NT + threadIdx.x; s < A.prev_n_slots; s += (int64_t)gridDim.x * NT)
     reduce_shift(A.prev_partials, s, A.n_cb, A.nacc, A.prev_a0, A.prev_rows, A.nf, A.qa, A.prev_shift_sums);
-  colpass_tiles<T, NT, RB, NH, CB, QM, SPLIT, true>(A, blockIdx.x, gridDim.x, lds, red);
+  colpass_tiles<T, NT, RB, NH, CB, QM, SPLIT, true, true>(A, blockIdx.x, gridDim.x, lds, red);
 }
 
 // Backward row pass: rows of 2^NL adjoint values, read in the row pass's output layout (register

@@ -235,7 +235,8 @@ struct ColShape {
 // ADJ (gradient): after the sums, each value is replaced by its adjoint seed |k U|^{2q-2} U, the
 // column stages run again in reverse order (the transform is its own adjoint) and the tile is
 // written back in place.
-template <typename T, int NT, int RB, int NH, int CB, int QM, bool SPLIT, bool ADJ = false>
+// XCD: tiles t0, t0 + tstep, ... are taken through xcd_tile (tstep a multiple of 8).
+template <typename T, int NT, int RB, int NH, int CB, int QM, bool SPLIT, bool ADJ = false, bool XCD = false>
 __device__ __forceinline__ void colpass_tiles(const ColPassArgs &A, int64_t t0, int64_t tstep,
                                               typename ColShape<T, NT, RB, NH, CB, SPLIT>::Elem *lds, double *red) {
   constexpr int R = 1 << RB;
@@ -250,7 +251,8 @@ __device__ __forceinline__ void colpass_tiles(const ColPassArgs &A, int64_t t0, 
   const uint32_t col = tau & ((1u << CB) - 1u);
   const uint32_t rowhi = tau >> CB;
 
-  for (int64_t tile = t0; tile < A.n_tiles; tile += tstep) {
+  for (int64_t b = t0; b < A.n_tiles; b += tstep) {
+    const int64_t tile = XCD ? xcd_tile(b, A.n_tiles) : b;
     const int64_t slot = tile / A.n_cb;
     const int64_t cb = tile - slot * A.n_cb;
     T re[R], im[R];
@@ -338,7 +340,7 @@ __global__ __launch_bounds__(NT) void k_sre_colpass(ColPassArgs A) {
   __shared__ double red[NT / 64 + 1];
   for (int64_t s = (int64_t)blockIdx.x * NT + threadIdx.x; s < A.prev_n_slots; s += (int64_t)gridDim.x * NT)
     reduce_shift(A.prev_partials, s, A.n_cb, A.nacc, A.prev_a0, A.prev_rows, A.nf, A.qa, A.prev_shift_sums);
-  colpass_tiles<T, NT, RB, NH, CB, QM, SPLIT>(A, blockIdx.x, gridDim.x, lds, red);
+  colpass_tiles<T, NT, RB, NH, CB, QM, SPLIT, false, true>(A, blockIdx.x, gridDim.x, lds, red);
 }
 
 // per-shift sums from column-pass partials of the last batch

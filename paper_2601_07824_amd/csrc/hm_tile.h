@@ -135,6 +135,17 @@ __device__ __forceinline__ void relayout_split(T (&re)[R], T (&im)[R], T *lds, u
   relayout_one<T, R, RB, SA, SB>(im, lds, tau);
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b runs on XCD b mod 8).  This
+// maps b in [0, n) to a tile so that XCD k takes the k-th contiguous share of [0, n) (a bijection
+// for every n; shares differ by at most one tile): neighbouring tiles, which share cache lines of
+// the exchange rows, are then read through the same L2.
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t n) {
+  const int64_t k = b & 7, m = b >> 3;
+  int64_t start = 0;
+  for (int64_t i = 0; i < k; ++i) start += (n - i + 7) >> 3;
+  return start + m;
+}
+
 // Deterministic sum over aligned segments of SEG consecutive threads (SEG a power of two dividing
 // NT).  Returns the segment total in the first thread of each segment (other threads: partial).
 // lds must hold NT/64 doubles per value.

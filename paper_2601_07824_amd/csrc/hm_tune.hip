@@ -34,7 +34,7 @@ PlanOpts plan_opts(const hm_context *h, int n, int dbl) {
 
 // Candidate plans for (n, dbl): the workgroup-resident kernel when it applies, and two-pass plans
 // over exchange batches of 64/128/256 MiB x LDS staging x {sequential with the default split or
-// 11 or 12 row bits, pipelined}.  Options the caller fixed on the handle are kept.
+// 11, 12 or 13 row bits, pipelined}.  Options the caller fixed on the handle are kept.
 static std::vector<PlanOpts> candidates(const hm_context *h, int n, int dbl) {
   std::vector<PlanOpts> c;
   auto add = [&](PlanOpts o) {
@@ -66,13 +66,13 @@ static std::vector<PlanOpts> candidates(const hm_context *h, int n, int dbl) {
     if (b == last_b) continue;
     last_b = b;
     for (int split : {1, 2})
-      for (int v = 0; v < 4; ++v) {
+      for (int v = 0; v < 5; ++v) {
         PlanOpts o{};
         o.force_path = 2;
         o.batch = b;
         o.lds_split = split;
-        o.pipeline = v == 3 ? 2 : 1;
-        o.row_bits = v == 1 ? 12 : v == 2 ? 11 : 0;
+        o.pipeline = v == 4 ? 2 : 1;
+        o.row_bits = v == 1 ? 12 : v == 2 ? 11 : v == 3 ? 13 : 0;
         add(o);
       }
   }

@@ -68,6 +68,21 @@ def test_two_pass_n9_vs_oracle(orc, hm, c64):
     assert abs(got[0] - want[0]) <= TOL[c64] * max(1.0, abs(want[0])), (got, want)
 
 
+@pytest.mark.parametrize("batch", [7, 64])
+def test_two_pass_batches(orc, hm, batch):
+    """Launch batches of 7 shifts (rounded up to 4 shift pairs; ragged last launch) and of 64 at
+    n = 10, complex128."""
+    n = 10
+    psi = S.gaussian_state(n, d=3, seed=5020)
+    x, w = gpu_state(psi, False)
+    ctx = hm.Context()
+    ctx.batch_shifts(batch)
+    say(f"[mana batch] n={n} batch={batch}")
+    got = hm.mana(x, ctx=ctx).cpu().numpy()
+    want = orc.mana_fft(w)
+    assert abs(got[0] - want[0]) <= 1e-10 * max(1.0, abs(want[0])), (got, want)
+
+
 def test_golden_values(hm):
     gold = json.load(open(GOLDEN))
     for key, n, c64, seed in (("mana_gauss_n8_seed5008_c128", 8, False, 5008), ("mana_gauss_n10_seed5010_c64", 10, True, 5010)):
