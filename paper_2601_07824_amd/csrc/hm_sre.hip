@@ -201,10 +201,11 @@ int sre_plan(int N, int dbl, const PlanOpts &o, SrePlan *p) {
     if (o.pipeline == 2 && !sre_pipe_built(P))
       return fail(E_UNSUPPORTED, "SRE: no pipelined kernels for n = %d with these tiles", N);
     if (o.pipeline == 2 || (o.pipeline == 0 && SRE_PIPE_DEFAULT && sre_pipe_built(P))) P.pipe = 1;
-    // Split LDS staging (half the LDS per workgroup) exists for the default register tiles only.
-    const bool split_ok = row_rb == RB && col_rb == RB;
+    // Split LDS staging (half the LDS per workgroup) exists for the default column tiles and for
+    // row tiles of 2^4 or 2^5 (FP32) / 2^4 (FP64) values.
+    const bool split_ok = col_rb == RB && (row_rb == RB || row_rb == 4);
     if (o.lds_split == 2 && !split_ok)
-      return fail(E_UNSUPPORTED, "SRE: split LDS staging needs the default register tiles (2^%d)", RB);
+      return fail(E_UNSUPPORTED, "SRE: split LDS staging needs the default column register tiles (2^%d)", RB);
     P.split = split_ok && (o.lds_split == 2 || (o.lds_split == 0 && !dbl && SRE_SPLIT_DEFAULT));
     // Untuned batch: 256 MiB of exchange per FP32 launch (measured best at n = 20 on MI355X: the
     // launch count matters more than staying inside the 256 MiB MALL), 128 MiB for FP64; pipelined

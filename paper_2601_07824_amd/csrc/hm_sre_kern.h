@@ -79,7 +79,6 @@ __device__ __forceinline__ void rowpass_tiles(const RowPassArgs &A, int64_t t0, 
   constexpr int SEG = 1 << S0;           // threads per row-task
   constexpr int G = 1 << (TB - NL);      // row-tasks per tile
   constexpr bool WAVE_UNIFORM = SEG >= 64;
-  constexpr int LDS_N = (K > 1) ? ((1 << TB) + (1 << (TB - RB))) : 1;
 
   const vec2<T> *__restrict__ psi = (const vec2<T> *)A.psi;
   const uint32_t tau = threadIdx.x;
@@ -433,12 +432,12 @@ static int launch_rowwrite_rb(int NL, RowPassArgs A, hipStream_t st) {
   return fail(E_UNSUPPORTED, "row pass: no kernel for rows of 2^%d values (RB %d)", NL, RB);
 }
 
-// Split LDS staging is built for the default register tiles (2^5 FP32, 2^4 FP64) only.
+// Split LDS staging is built for 2^5 and 2^4 FP32 and 2^4 FP64 register tiles.
 template <typename T>
 static int launch_rowwrite(int rb, int NL, RowPassArgs A, bool split, hipStream_t st) {
   if constexpr (sizeof(T) == 4) {
     if (rb == 5) return split ? launch_rowwrite_rb<T, 5, true>(NL, A, st) : launch_rowwrite_rb<T, 5, false>(NL, A, st);
-    if (rb == 4 && !split) return launch_rowwrite_rb<T, 4, false>(NL, A, st);
+    if (rb == 4) return split ? launch_rowwrite_rb<T, 4, true>(NL, A, st) : launch_rowwrite_rb<T, 4, false>(NL, A, st);
   } else {
     if (rb == 4) return split ? launch_rowwrite_rb<T, 4, true>(NL, A, st) : launch_rowwrite_rb<T, 4, false>(NL, A, st);
   }

@@ -186,6 +186,8 @@ def test_planner_accepts_every_configuration_the_gpu_tests_use():
             cases.append((o, n, dt))
     for dt, n in ((1, 11), (1, 13), (0, 12), (0, 14)):
         cases.append(([(FP, 2), (BS, 7), (SPLIT, 2)], n, dt))
+    for n in (13, 15):
+        cases.append(([(FP, 2), (BS, 7), (SPLIT, 2), (RRB, 4)], n, 0))
     for n in (16, 20):
         cases += [([(PIPE, 1), (RB, 12 if n == 20 else 0), (SPLIT, 2)], n, 0), ([(PIPE, 1), (SPLIT, 2)], n, 1)]
     for dt, n in ((1, 13), (1, 14), (1, 15), (0, 14), (0, 15), (0, 16)):

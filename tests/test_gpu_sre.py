@@ -110,13 +110,17 @@ def test_forced_two_pass(orc, hm, n, c64, rb):
         assert rel_err(got[:-1], want[:-1]) < TOL[c64], (got, want)
 
 
-@pytest.mark.parametrize("c64,n", [(False, 11), (False, 13), (True, 12), (True, 14)])
-def test_two_pass_split_lds(orc, hm, n, c64):
-    """Sequential two-pass kernels with split LDS staging (real and imaginary parts in turn)."""
+@pytest.mark.parametrize("c64,n,row_rb", [(False, 11, 0), (False, 13, 0), (True, 12, 0), (True, 14, 0), (True, 13, 4),
+                                          (True, 15, 4)])
+def test_two_pass_split_lds(orc, hm, n, c64, row_rb):
+    """Sequential two-pass kernels with split LDS staging (real and imaginary parts in turn), also
+    with 2^4-value row tiles."""
     ctx = hm.Context()
     ctx.force_path(2)
     ctx.batch_shifts(7)
     ctx.set_option(hm.OPT_LDS_SPLIT, 2)
+    if row_rb:
+        ctx.set_option(hm.OPT_ROW_RB, row_rb)
     psi = S.brickwall_haar(n, 2 * n, seed=3040 + n)
     x, w = gpu_state(psi, c64)
     for q in ((2.0,), (1.0, 3.0)):
