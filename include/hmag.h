@@ -81,6 +81,10 @@ const char *hm_version(void);
  *   HM_OPT_LDS_SPLIT: two-pass kernels with the default register tiles, 1 = stage complex values
  *     through LDS, 2 = stage real and imaginary parts one after the other (half the LDS per
  *     workgroup, so more workgroups per CU).
+ *   HM_OPT_STREAMS: sequential two-pass launches on 1 stream (the caller's) or 2 (batches alternate
+ *     between the caller's stream and an internal stream of the library, forked from and joined
+ *     back into the caller's stream with events, so results stay stream-ordered; twice the
+ *     exchange workspace).
  * A combination outside the built kernels makes the SRE calls return HM_E_UNSUPPORTED. */
 typedef enum {
   HM_OPT_FORCE_PATH = 1,
@@ -89,14 +93,16 @@ typedef enum {
   HM_OPT_COL_RB = 4,
   HM_OPT_ROW_BITS = 5,
   HM_OPT_PIPELINE = 6,
-  HM_OPT_LDS_SPLIT = 7
+  HM_OPT_LDS_SPLIT = 7,
+  HM_OPT_STREAMS = 8
 } hm_option;
 hm_status hm_set_option(hm_handle h, hm_option opt, int64_t value);
 
 /* Autotuner.  Times every candidate SRE plan for (n, dtype) on the state psi (device) over the
  * first sample_shifts X-shifts (16384 if <= 0, at most 2^n): the workgroup-resident kernel where it
  * applies, and two-pass plans over exchange batches of 64/128/256 MiB, both LDS stagings,
- * sequential launches with the default, 11, 12 or 13 row bits, and pipelined launches.  Options
+ * sequential launches (one or two streams) with the default, 11, 12 or 13 row bits, and pipelined
+ * launches.  Options
  * already set on the handle are kept fixed.  The fastest plan is stored in the handle; later calls
  * on the handle for the same (n, dtype) fill every option left automatic from it.  Candidates
  * whose workspace exceeds ws_bytes are skipped (hm_autotune_workspace gives the size that admits
@@ -105,9 +111,10 @@ hm_status hm_set_option(hm_handle h, hm_option opt, int64_t value);
 hm_status hm_autotune_workspace(hm_handle h, int n, hm_dtype dtype, int64_t sample_shifts, size_t *bytes);
 hm_status hm_autotune(hm_handle h, const void *psi, int n, hm_dtype dtype, int64_t sample_shifts, void *ws,
                       size_t ws_bytes, hipStream_t stream);
-/* The stored plan for (n, dtype): opts[0..6] = {HM_OPT_FORCE_PATH, HM_OPT_BATCH_SHIFTS,
- * HM_OPT_ROW_RB, HM_OPT_COL_RB, HM_OPT_ROW_BITS, HM_OPT_PIPELINE, HM_OPT_LDS_SPLIT} values (host
- * array of 7), and its measured milliseconds per X-shift.  HM_E_ARG if none is stored. */
+/* The stored plan for (n, dtype): opts[0..7] = {HM_OPT_FORCE_PATH, HM_OPT_BATCH_SHIFTS,
+ * HM_OPT_ROW_RB, HM_OPT_COL_RB, HM_OPT_ROW_BITS, HM_OPT_PIPELINE, HM_OPT_LDS_SPLIT, HM_OPT_STREAMS}
+ * values (host array of 8), and its measured milliseconds per X-shift.  HM_E_ARG if none is
+ * stored. */
 hm_status hm_tune_query(hm_handle h, int n, hm_dtype dtype, int64_t *opts, double *ms_per_shift);
 /* Forgets every stored plan of the handle. */
 hm_status hm_tune_clear(hm_handle h);

@@ -28,7 +28,8 @@ lib_path = os.path.join(_HERE, "libhmag.so")
 
 HM_C64, HM_C128 = 0, 1
 OP_SRE, OP_SRE_ROWS, OP_ROW_VALUES, OP_SRE_GRAD, OP_MANA, OP_SRE_SAMPLED = 0, 1, 2, 3, 4, 5
-OPT_FORCE_PATH, OPT_BATCH_SHIFTS, OPT_ROW_RB, OPT_COL_RB, OPT_ROW_BITS, OPT_PIPELINE, OPT_LDS_SPLIT = 1, 2, 3, 4, 5, 6, 7
+OPT_FORCE_PATH, OPT_BATCH_SHIFTS, OPT_ROW_RB, OPT_COL_RB, OPT_ROW_BITS, OPT_PIPELINE, OPT_LDS_SPLIT, OPT_STREAMS = \
+    1, 2, 3, 4, 5, 6, 7, 8
 
 _vp = ctypes.c_void_p
 _i = ctypes.c_int
@@ -283,7 +284,7 @@ def sre_rows(psi, rows, q=(2.0,), *, ctx: Context | None = None, stream=None):
     return out
 
 
-TUNE_KEYS = ("force_path", "batch_shifts", "row_rb", "col_rb", "row_bits", "pipeline", "lds_split")
+TUNE_KEYS = ("force_path", "batch_shifts", "row_rb", "col_rb", "row_bits", "pipeline", "lds_split", "streams")
 
 
 def autotune(psi, sample_shifts: int = 16384, *, ctx: Context | None = None, stream=None) -> dict:
@@ -302,7 +303,7 @@ def autotune(psi, sample_shifts: int = 16384, *, ctx: Context | None = None, str
 def tuned_plan(n: int, dtype_code: int, *, ctx: Context | None = None) -> dict:
     """The plan the autotuner stored for (n, dtype code), with its milliseconds per X-shift."""
     ctx = ctx or default_context()
-    v = (_i64 * 7)()
+    v = (_i64 * 8)()
     ms = ctypes.c_double(0.0)
     _check(lib().hm_tune_query(ctx.h, n, dtype_code, v, ctypes.byref(ms)))
     d = dict(zip(TUNE_KEYS, [int(x) for x in v]))

@@ -146,6 +146,10 @@ hm_status hm_set_option(hm_handle h, hm_option opt, int64_t value) {
       if (value < 0 || value > 2) return (hm_status)fail(E_ARG, "HM_OPT_LDS_SPLIT %lld not in {0,1,2}", (long long)value);
       h->opts.lds_split = (int)value;
       return HM_OK;
+    case HM_OPT_STREAMS:
+      if (value < 0 || value > 2) return (hm_status)fail(E_ARG, "HM_OPT_STREAMS %lld not in {0,1,2}", (long long)value);
+      h->opts.streams = (int)value;
+      return HM_OK;
   }
   return (hm_status)fail(E_ARG, "unknown option %d", (int)opt);
 }
@@ -414,8 +418,8 @@ hm_status hm_tune_query(hm_handle h, int n, hm_dtype dtype, int64_t *opts, doubl
   for (const auto &t : h->tuned)
     if (t.n == n && t.dbl == (dtype == HM_C128)) {
       const PlanOpts &o = t.opts;
-      const int64_t v[7] = {o.force_path, o.batch, o.row_rb, o.col_rb, o.row_bits, o.pipeline, o.lds_split};
-      for (int i = 0; i < 7; ++i) opts[i] = v[i];
+      const int64_t v[8] = {o.force_path, o.batch, o.row_rb, o.col_rb, o.row_bits, o.pipeline, o.lds_split, o.streams};
+      for (int i = 0; i < 8; ++i) opts[i] = v[i];
       if (ms_per_shift) *ms_per_shift = t.ms_per_shift;
       return HM_OK;
     }

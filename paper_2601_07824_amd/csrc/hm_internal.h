@@ -48,6 +48,7 @@ struct SrePlan {
   int col_rb;   // register-tile bits of the column pass
   int pipe;     // 1: row pass of batch k and column pass of batch k-1 share one launch
   int split;    // 1: pipelined tiles stage one component at a time through LDS (half the LDS)
+  int streams;  // 2: sequential batches alternate between the caller's stream and an internal one
 };
 
 // Default two-pass split.  Column tiles hold 2^col_tb values; the row pass takes about half of the
@@ -71,6 +72,9 @@ inline bool sre_pipe_built(const SrePlan &p) {
          p.row_rb == rb && p.col_rb == rb &&
          p.col_tb == sre_default_col_tb(p.nf, p.dbl, rb) && p.nl == sre_default_nl(p.nf, p.col_tb, rb);
 }
+// Internal stream of the current device (created on first use, default priority, non-blocking),
+// used as the second stream of two-stream plans.
+int side_stream(hipStream_t *st);
 // Workspace pieces of the two-pass path: exchange buffer(s) and per-column-block partials.
 inline size_t sre_exch_bytes(const SrePlan &p) {
   if (p.path != 2) return 0;
@@ -88,6 +92,7 @@ struct PlanOpts {
   int row_bits = 0;
   int pipeline = 0;  // 0 automatic, 1 off, 2 on
   int lds_split = 0; // 0 automatic, 1 off, 2 on
+  int streams = 0;   // 0 automatic, 1 or 2
 };
 
 // Plan options chosen by the autotuner for one (qubit count, dtype).

@@ -156,11 +156,22 @@ __global__ __launch_bounds__(NT) void k_mana_rowpass(ManaRowArgs A) {
   const bool tact = g < (uint32_t)G;
   double m_acc = 0.0, s_acc = 0.0, q_acc = 0.0;
 
-  for (int64_t tile = blockIdx.x; tile < A.n_tiles; tile += gridDim.x) {
+  // WRITE: row-tasks are numbered xh-major (rt = xh * n_pairs + pair) and each XCD takes a
+  // contiguous share of the tiles, so an XCD works on a fixed set of rows xh for every shift pair of
+  // the launch and reads a fixed eighth-or-so of the state through its L2.
+  for (int64_t b = blockIdx.x; b < A.n_tiles; b += gridDim.x) {
+    const int64_t tile = WRITE ? xcd_tile(b, A.n_tiles) : b;  // gridDim is a multiple of 8
     const int64_t rt = tile * G + g;
-    const int64_t pair = rt / A.nhr;
-    const uint32_t xh = (uint32_t)(rt - pair * A.nhr);
-    const bool active = tact && pair < A.n_pairs;
+    int64_t pair;
+    uint32_t xh;
+    if constexpr (WRITE) {
+      xh = (uint32_t)(rt / A.n_pairs);
+      pair = rt - (int64_t)xh * A.n_pairs;
+    } else {
+      pair = rt / A.nhr;
+      xh = (uint32_t)(rt - pair * A.nhr);
+    }
+    const bool active = tact && (WRITE ? rt < A.n_pairs * A.nhr : pair < A.n_pairs);
     T re[R], im[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) re[r] = im[r] = T(0);
@@ -174,10 +185,34 @@ __global__ __launch_bounds__(NT) void k_mana_rowpass(ManaRowArgs A) {
         const uint32_t alo = al % (uint32_t)pow3c(S0), ahi = al / (uint32_t)pow3c(S0);
         const uint32_t xm = dsub3(xh, ah, A.nh, false) * ROWLEN + dsub3(tp, alo, S0, false);
         const uint32_t xn = dsub3(xh, ah, A.nh, true) * ROWLEN + dsub3(tp, alo, S0, true);
+        // Register trit i of r contributes ((r_i - h_i) mod 3) 3^(S0+i) to the index of alpha_x and
+        // ((-r_i - h_i) mod 3) 3^(S0+i) to that of alpha_{-x} (h = ahi): tables of the three
+        // possible contributions per trit, so that each register's offset is a sum of table entries
+        // picked by its (compile-time) digits.
+        uint32_t om[RT][3], on[RT][3];
+        {
+          uint32_t h = ahi, p = (uint32_t)pow3c(S0);
+#pragma unroll
+          for (int i = 0; i < RT; ++i) {
+            const uint32_t hd = h % 3u;
+            h /= 3u;
+#pragma unroll
+            for (int t = 0; t < 3; ++t) {
+              om[i][t] = ((3u + (uint32_t)t - hd) % 3u) * p;
+              on[i][t] = ((6u - (uint32_t)t - hd) % 3u) * p;
+            }
+            p *= 3u;
+          }
+        }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          const uint32_t rm = dsub3((uint32_t)r, ahi, RT, false) * (uint32_t)pow3c(S0);
-          const uint32_t rn = dsub3((uint32_t)r, ahi, RT, true) * (uint32_t)pow3c(S0);
+          uint32_t rm = 0, rn = 0;
+#pragma unroll
+          for (int i = 0; i < RT; ++i) {
+            const int t = (r / pow3c(i)) % 3;
+            rm += om[i][t];
+            rn += on[i][t];
+          }
           const vec2<T> p = ld32(psi, xm + rm);  // alpha_x
           const vec2<T> q = ld32(psi, xn + rn);  // alpha_{-x}
           const T vr = fmaT(p.x, q.x, p.y * q.y);   // conj(p) q
@@ -210,7 +245,7 @@ __global__ __launch_bounds__(NT) void k_mana_rowpass(ManaRowArgs A) {
       // (a fixed column permutation) so that consecutive threads write consecutive addresses.
       if (active) {
         vec2<T> *ex = (vec2<T> *)A.exch;
-        const uint32_t ob = (uint32_t)rt * ROWLEN + tp;
+        const uint32_t ob = ((uint32_t)pair * (uint32_t)A.nhr + xh) * ROWLEN + tp;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           vec2<T> v;

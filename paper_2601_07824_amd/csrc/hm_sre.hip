@@ -19,6 +19,8 @@
 //     runs the remaining NH stages and reduces.
 //   * shift reduce / final reduce: fixed-order FP64 sums (bitwise reproducible).
 #include <hip/hip_runtime.h>
+
+#include <mutex>
 #include <math.h>
 #include <stdint.h>
 
@@ -155,6 +157,19 @@ __global__ __launch_bounds__(256) void k_sre_total(const double *shift_sums, int
   }
 }
 
+// ---- internal streams -----------------------------------------------------------------------------
+int side_stream(hipStream_t *st) {
+  static std::mutex mu;
+  static hipStream_t streams[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return fail(E_HIP, "SRE: no current device");
+  std::lock_guard<std::mutex> g(mu);
+  if (!streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess)
+    return fail(E_HIP, "SRE: internal stream creation failed");
+  *st = streams[dev];
+  return OK;
+}
+
 // ---- planning -------------------------------------------------------------------------------------
 // Defaults (tuned on MI355X; see hm_autotune): FP32 register tiles of 2^5 values, FP64 of 2^4; the
 // two-pass split puts ceil(nf / 2) index bits in the row pass.  Every choice can be overridden
@@ -162,6 +177,7 @@ __global__ __launch_bounds__(256) void k_sre_total(const double *shift_sums, int
 // Pipelined launches (row pass of batch k with the column pass of batch k - 1) and split LDS staging
 // (two-pass kernels) are used automatically when these are set.
 static constexpr bool SRE_PIPE_DEFAULT = false, SRE_SPLIT_DEFAULT = true;
+static constexpr int SRE_STREAMS_DEFAULT = 1;
 
 int sre_plan(int N, int dbl, const PlanOpts &o, SrePlan *p) {
   if (N < 1 || N > 26) return fail(E_SIZE, "SRE: n = %d outside [1, 26]", N);
@@ -207,6 +223,8 @@ int sre_plan(int N, int dbl, const PlanOpts &o, SrePlan *p) {
     if (o.lds_split == 2 && !split_ok)
       return fail(E_UNSUPPORTED, "SRE: split LDS staging needs the default column register tiles (2^%d)", RB);
     P.split = split_ok && (o.lds_split == 2 || (o.lds_split == 0 && !dbl && SRE_SPLIT_DEFAULT));
+    if (o.streams == 2 && P.pipe) return fail(E_UNSUPPORTED, "SRE: two streams apply to sequential launches only");
+    P.streams = (o.streams == 2 || (o.streams == 0 && SRE_STREAMS_DEFAULT == 2 && !P.pipe)) ? 2 : 1;
     // Untuned batch: 256 MiB of exchange per FP32 launch (measured best at n = 20 on MI355X: the
     // launch count matters more than staying inside the 256 MiB MALL), 128 MiB for FP64; pipelined
     // launches hold two buffers.
@@ -228,8 +246,9 @@ size_t sre_workspace(const SrePlan &p, int nq, int64_t n_internal_slots) {
   const size_t nacc = (size_t)nq + 1;
   size_t b = align256((size_t)n_internal_slots * nacc * sizeof(double));
   if (p.path == 2) {
-    b += sre_exch_bytes(p);
-    b += 2 * align256((size_t)p.batch * (size_t)sre_col_blocks(p) * nacc * sizeof(double));  // double-buffered
+    const size_t lane = sre_exch_bytes(p) + 2 * align256((size_t)p.batch * (size_t)sre_col_blocks(p) * nacc *
+                                                         sizeof(double));  // double-buffered partials
+    b += (p.streams == 2 ? 2 : 1) * lane;
   }
   return b < 256 ? 256 : b;
 }

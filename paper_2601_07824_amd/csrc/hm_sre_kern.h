@@ -516,13 +516,42 @@ int shift_sums_t(const SrePlan &p, const void *psi, const QArgs &qa, uint64_t a0
   // column-block partials and reduces the previous batch's partials to per-shift sums).
   if (p.pipe) return sizeof(T) == 4 ? sre_pipe_f32(p, psi, qa, a0, rows, n_slots, shift_sums, w, st)
                                     : sre_pipe_f64(p, psi, qa, a0, rows, n_slots, shift_sums, w, st);
+  // Sequential launches on one or two streams.  With two streams, batch k goes to stream k mod 2
+  // (the caller's stream and an internal one forked from it), each with its own exchange buffer and
+  // partials, so one stream's row pass (exchange writes) overlaps the other's column pass (reads).
   const int64_t n_cb = sre_col_blocks(p);
-  void *exch = w;
+  const int L = p.streams == 2 && n_slots > p.batch ? 2 : 1;
+  const size_t xb = sre_exch_bytes(p);
   const size_t pbytes = align256((size_t)p.batch * (size_t)n_cb * nacc * sizeof(double));
-  double *partials[2] = {(double *)(w + sre_exch_bytes(p)), (double *)(w + sre_exch_bytes(p) + pbytes)};
-  int64_t prev_s0 = 0, prev_nb = 0;
-  int k = 0;
-  for (int64_t s0 = 0; s0 < n_slots; s0 += p.batch, ++k) {
+  struct Lane {
+    hipStream_t st;
+    void *exch;
+    double *partials[2];
+    int64_t prev_s0, prev_nb;
+    int k;
+  } lane[2];
+  for (int l = 0; l < L; ++l) {
+    char *b = w + (size_t)l * (xb + 2 * pbytes);
+    lane[l].exch = b;
+    lane[l].partials[0] = (double *)(b + xb);
+    lane[l].partials[1] = (double *)(b + xb + pbytes);
+    lane[l].prev_s0 = lane[l].prev_nb = 0;
+    lane[l].k = 0;
+  }
+  lane[0].st = st;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  if (L == 2) {
+    int e = side_stream(&lane[1].st);
+    if (e) return e;
+    if (hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ev_join, hipEventDisableTiming) != hipSuccess)
+      return fail(E_HIP, "SRE: event creation failed");
+    if (hipEventRecord(ev_fork, st) != hipSuccess || hipStreamWaitEvent(lane[1].st, ev_fork, 0) != hipSuccess)
+      return fail(E_HIP, "SRE: stream fork failed");
+  }
+  int64_t bi = 0;
+  for (int64_t s0 = 0; s0 < n_slots; s0 += p.batch, ++bi) {
+    Lane &ln = lane[bi % L];
     const int64_t nb = (n_slots - s0) < p.batch ? (n_slots - s0) : p.batch;
     RowPassArgs A{};
     A.psi = psi;
@@ -531,35 +560,43 @@ int shift_sums_t(const SrePlan &p, const void *psi, const QArgs &qa, uint64_t a0
     A.n_slots = nb;
     A.a0 = a0 + (uint64_t)s0;
     A.rows = rows ? rows + s0 : nullptr;
-    A.exch = exch;
+    A.exch = ln.exch;
     A.nacc = nacc;
     A.qa = qa;
-    int e = launch_rowwrite<T>(p.row_rb, p.nl, A, p.split != 0, st);
+    int e = launch_rowwrite<T>(p.row_rb, p.nl, A, p.split != 0, ln.st);
     if (e) return e;
     ColPassArgs C{};
-    C.exch = exch;
+    C.exch = ln.exch;
     C.nl = p.nl;
     C.n_slots = nb;
-    C.partials = partials[k & 1];
+    C.partials = ln.partials[ln.k & 1];
     C.nacc = nacc;
     C.qa = qa;
     C.nf = p.nf;
-    C.prev_partials = partials[(k + 1) & 1];
-    C.prev_n_slots = prev_nb;
-    C.prev_a0 = a0 + (uint64_t)prev_s0;
-    C.prev_rows = rows ? rows + prev_s0 : nullptr;
-    C.prev_shift_sums = shift_sums + prev_s0 * nacc;
-    e = launch_colpass<T>(p.col_rb, p.col_tb, p.nh, C, q2, p.split != 0, st);
+    C.prev_partials = ln.partials[(ln.k + 1) & 1];
+    C.prev_n_slots = ln.prev_nb;
+    C.prev_a0 = a0 + (uint64_t)ln.prev_s0;
+    C.prev_rows = rows ? rows + ln.prev_s0 : nullptr;
+    C.prev_shift_sums = shift_sums + ln.prev_s0 * nacc;
+    e = launch_colpass<T>(p.col_rb, p.col_tb, p.nh, C, q2, p.split != 0, ln.st);
     if (e) return e;
-    prev_s0 = s0;
-    prev_nb = nb;
+    ln.prev_s0 = s0;
+    ln.prev_nb = nb;
+    ++ln.k;
   }
-  {
+  for (int l = 0; l < L; ++l) {
+    Lane &ln = lane[l];
     const int thr = 128;
-    ProfScope prof("sre_shift_reduce", st);
-    hipLaunchKernelGGL(k_sre_shift_reduce, dim3((unsigned)((prev_nb + thr - 1) / thr)), dim3(thr), 0, st,
-                       partials[(k + 1) & 1], prev_nb, n_cb, nacc, a0 + (uint64_t)prev_s0,
-                       rows ? rows + prev_s0 : nullptr, p.nf, qa, shift_sums + prev_s0 * nacc);
+    ProfScope prof("sre_shift_reduce", ln.st);
+    hipLaunchKernelGGL(k_sre_shift_reduce, dim3((unsigned)((ln.prev_nb + thr - 1) / thr)), dim3(thr), 0, ln.st,
+                       ln.partials[(ln.k + 1) & 1], ln.prev_nb, n_cb, nacc, a0 + (uint64_t)ln.prev_s0,
+                       rows ? rows + ln.prev_s0 : nullptr, p.nf, qa, shift_sums + ln.prev_s0 * nacc);
+  }
+  if (L == 2) {
+    const bool ok = hipEventRecord(ev_join, lane[1].st) == hipSuccess && hipStreamWaitEvent(st, ev_join, 0) == hipSuccess;
+    (void)hipEventDestroy(ev_fork);
+    (void)hipEventDestroy(ev_join);
+    if (!ok) return fail(E_HIP, "SRE: stream join failed");
   }
   return hipPeekAtLastError() == hipSuccess ? OK : fail(E_HIP, "SRE two-pass launch: %s", hipGetErrorString(hipGetLastError()));
 }

@@ -27,6 +27,7 @@ PlanOpts plan_opts(const hm_context *h, int n, int dbl) {
     if (!o.row_bits) o.row_bits = t.opts.row_bits;
     if (!o.pipeline) o.pipeline = t.opts.pipeline;
     if (!o.lds_split) o.lds_split = t.opts.lds_split;
+    if (!o.streams) o.streams = t.opts.streams;
     break;
   }
   return o;
@@ -47,6 +48,7 @@ static std::vector<PlanOpts> candidates(const hm_context *h, int n, int dbl) {
     if (u.row_bits) o.row_bits = u.row_bits;
     if (u.pipeline) o.pipeline = u.pipeline;
     if (u.lds_split) o.lds_split = u.lds_split;
+    if (u.streams) o.streams = u.streams;
     SrePlan p;
     if (sre_plan(n, dbl, o, &p) != OK) return;
     for (const auto &e : c)
@@ -73,7 +75,12 @@ static std::vector<PlanOpts> candidates(const hm_context *h, int n, int dbl) {
         o.lds_split = split;
         o.pipeline = v == 4 ? 2 : 1;
         o.row_bits = v == 1 ? 12 : v == 2 ? 11 : v == 3 ? 13 : 0;
+        o.streams = 1;
         add(o);
+        if (v < 4) {  // the same on two streams
+          o.streams = 2;
+          add(o);
+        }
       }
   }
   return c;

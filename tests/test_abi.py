@@ -188,6 +188,8 @@ def test_planner_accepts_every_configuration_the_gpu_tests_use():
         cases.append(([(FP, 2), (BS, 7), (SPLIT, 2)], n, dt))
     for n in (13, 15):
         cases.append(([(FP, 2), (BS, 7), (SPLIT, 2), (RRB, 4)], n, 0))
+    for dt, n in ((1, 12), (1, 14), (0, 12), (0, 15), (0, 20), (1, 20)):
+        cases.append(([(FP, 2), (BS, 5), (8, 2)], n, dt))
     for n in (16, 20):
         cases += [([(PIPE, 1), (RB, 12 if n == 20 else 0), (SPLIT, 2)], n, 0), ([(PIPE, 1), (SPLIT, 2)], n, 1)]
     for dt, n in ((1, 13), (1, 14), (1, 15), (0, 14), (0, 15), (0, 16)):

@@ -130,6 +130,28 @@ def test_two_pass_split_lds(orc, hm, n, c64, row_rb):
         assert rel_err(got[:-1], want[:-1]) < TOL[c64], (got, want)
 
 
+@pytest.mark.parametrize("c64,n", [(False, 12), (False, 14), (True, 12), (True, 15)])
+def test_two_pass_two_streams(orc, hm, n, c64):
+    """Sequential two-pass batches alternating between the caller's stream and the internal one:
+    full sums (ragged batches), a partial range and explicit rows, against the oracle."""
+    psi = S.brickwall_haar(n, 2 * n, seed=3060 + n)
+    x, w = gpu_state(psi, c64)
+    ctx = hm.Context()
+    ctx.force_path(2)
+    ctx.batch_shifts(5)
+    ctx.set_option(hm.OPT_STREAMS, 2)
+    say(f"[sre two streams] n={n} c64={c64}")
+    got = hm.sre(x, (1.0, 2.0), ctx=ctx).cpu().numpy()
+    want = orc.sre_fwht(w, (1.0, 2.0))
+    assert rel_err(got[:-1], want[:-1]) < TOL[c64], (got, want)
+    got = hm.sre_partial(x, (2.0,), 7, 40, ctx=ctx).cpu().numpy()
+    np.testing.assert_allclose(got, orc.sre_fwht_sums(w, (2.0,), 7, 40), rtol=(1e-11 if not c64 else 2e-6))
+    rows = S.uniform_rows(n, 23, seed=3061).astype(np.int64)
+    got = hm.sre_rows(x, rows, (2.0,), ctx=ctx).cpu().numpy()
+    want = orc.sre_rows(w, rows.astype(np.uint64), (2.0,))
+    assert rel_err(got, want, floor=1e-15) < (1e-10 if not c64 else 1e-5)
+
+
 @pytest.mark.parametrize("split", [1, 2])
 @pytest.mark.parametrize("c64,n", [(False, 12), (False, 13), (False, 14), (True, 12), (True, 13), (True, 15)])
 def test_pipelined_two_pass(orc, hm, n, c64, split):
