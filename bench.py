@@ -206,6 +206,8 @@ def main():
     ap.add_argument("--lds-split", type=int, default=0, choices=(0, 1, 2), help="HM_OPT_LDS_SPLIT")
     ap.add_argument("--row-bits", type=int, default=0, help="HM_OPT_ROW_BITS (0 = planner default)")
     ap.add_argument("--no-autotune", action="store_true", help="skip the plan autotuner (untimed, before warm-up)")
+    ap.add_argument("--mana-only", type=int, default=0, metavar="N",
+                    help="profiling runs: time only the qutrit mana of an N-qutrit complex64 state per step")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="counter calibration: time a plain device copy of this many MiB five times and exit")
     args = ap.parse_args()
@@ -222,6 +224,22 @@ def main():
     from synth import states as S
 
     dev = torch.device("cuda:0")
+    if args.mana_only:
+        n = args.mana_only
+        m = torch.from_numpy(S.to_c64_exact(S.gaussian_state(n, d=3, seed=1212))[0]).to(dev)
+        for _ in range(args.warmup):
+            hm.mana(m)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            o = hm.mana(m)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        print(json.dumps({"metric": "phase-space points/s (mana)", "value": 9.0 ** n / (ms * 1e-3),
+                          "unit": "phase-space points/s", "ms_per_step": ms, "steps": args.steps,
+                          "config": {"workload": f"mana, N={n} qutrits, complex64 Gaussian state, seed 1212"},
+                          "mana": float(o[0].item())}), flush=True)
+        return
     if args.copy_mib:
         n = args.copy_mib << 18  # float32 elements
         src = torch.ones(n, dtype=torch.float32, device=dev)
