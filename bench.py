@@ -213,7 +213,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the X-shift loop "
-              "would be sharded over GPUs with one all-reduce of the partial sums, see DESIGN.md)",
+              "would be sharded over GPUs, each evaluating hm_sre_partial on its share, with one all-reduce of "
+              "the partial sums)",
               file=sys.stderr)
         sys.exit(2)
 

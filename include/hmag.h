@@ -102,8 +102,7 @@ hm_status hm_set_option(hm_handle h, hm_option opt, int64_t value);
  * first sample_shifts X-shifts (16384 if <= 0, at most 2^n): the workgroup-resident kernel where it
  * applies, and two-pass plans over exchange batches of 64/128/256 MiB, both LDS stagings,
  * sequential launches (one or two streams) with the default, 11, 12 or 13 row bits, and pipelined
- * launches.  Options
- * already set on the handle are kept fixed.  The fastest plan is stored in the handle; later calls
+ * launches.  Options already set on the handle are kept fixed.  The fastest plan is stored in the handle; later calls
  * on the handle for the same (n, dtype) fill every option left automatic from it.  Candidates
  * whose workspace exceeds ws_bytes are skipped (hm_autotune_workspace gives the size that admits
  * all of them).  Blocks until the timings are done (it synchronises on events on `stream`).
@@ -195,8 +194,8 @@ hm_status hm_sre_batched(hm_handle h, const void *const *psis, const int *ns, in
 
 /* Monte Carlo estimate of M_2 from sampled X-rows (Sec. on sampling the Pauli spectrum; a row is
  * one transform, Eq. feP).  S(a) = sum_b |chi_b(a)|^4 and M_2 = -log2(mean over all a of S(a)).  The
- * row a = 0 holds the identity, whose single term <I>^4 = 1 dominates the sum for typical states
- * and would almost never be drawn, so that row is always evaluated exactly and the sampled rows
+ * row a = 0 holds the identity, whose single term <I>^4 = 1 is about a quarter of the sum for
+ * Haar-like states and would almost never be drawn, so that row is always evaluated exactly and the sampled rows
  * (caller-drawn, e.g. i.i.d. uniform in [1, 2^n); entries equal to 0 are skipped) estimate the
  * mean over a != 0:
  *   S_hat = (S(0) + (2^n - 1) mean_k S(a_k)) / 2^n,  M2_hat = -log2 S_hat.
