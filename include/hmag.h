@@ -78,9 +78,11 @@ const char *hm_version(void);
  *   HM_OPT_PIPELINE: two-pass launches, 1 = one row pass then one column pass per batch of
  *     shifts, 2 = pipelined (each launch runs the row pass of batch k beside the column pass of
  *     batch k - 1, with two exchange buffers; default tiles and split only).
- *   HM_OPT_LDS_SPLIT: two-pass kernels with the default register tiles, 1 = stage complex values
- *     through LDS, 2 = stage real and imaginary parts one after the other (half the LDS per
- *     workgroup, so more workgroups per CU).
+ *   HM_OPT_LDS_SPLIT: 1 = stage complex values through LDS, 2 = stage real and imaginary parts one
+ *     after the other (half the LDS per workgroup, so more workgroups per CU): two-pass kernels
+ *     with the default column register tiles, and workgroup-resident tiles of 2^10..2^14 (HM_C64)
+ *     or 2^10..2^13 (HM_C128) values, which then also keep to a register budget of three or four
+ *     waves per SIMD; the default for the resident tiles and for HM_C64 two-pass kernels.
  *   HM_OPT_STREAMS: sequential two-pass launches on 1 stream (the caller's) or 2 (batches alternate
  *     between the caller's stream and an internal stream of the library, forked from and joined
  *     back into the caller's stream with events, so results stay stream-ordered; twice the

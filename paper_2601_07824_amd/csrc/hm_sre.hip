@@ -196,6 +196,11 @@ int sre_plan(int N, int dbl, const PlanOpts &o, SrePlan *p) {
   if (path == 2 && P.nf < twopass_min)
     return fail(E_UNSUPPORTED, "SRE: two-pass path needs n >= %d", twopass_min + 1);
   P.path = path;
+  // Resident tiles of 2^10..2^14 (FP32) / 2^13 (FP64) values: split LDS staging with a higher
+  // occupancy register budget unless HM_OPT_LDS_SPLIT = 1 (measured 1.2-1.3x faster at n = 13, 14
+  // on MI355X).
+  if (path == 1)
+    P.split = (o.lds_split == 2 || (o.lds_split == 0 && SRE_SPLIT_DEFAULT)) && P.nf >= 10 && P.nf <= (dbl ? 13 : 14);
   if (path == 2) {
     const int row_rb = o.row_rb ? o.row_rb : RB;
     const int col_rb = o.col_rb ? o.col_rb : RB;

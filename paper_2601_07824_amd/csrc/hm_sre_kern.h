@@ -176,6 +176,16 @@ __global__ __launch_bounds__(NT) void k_sre_rowpass(RowPassArgs A) {
   rowpass_tiles<T, NT, RB, NL, WRITE, QM, SPLIT>(A, blockIdx.x, gridDim.x, lds, red);
 }
 
+// The same with a register budget for at least MINW waves per SIMD (resident tiles of <= 2^13
+// values with split LDS staging, so that LDS does not cap the occupancy either).
+template <typename T, int NT, int RB, int NL, int QM, int MINW>
+__global__ __launch_bounds__(NT, MINW) void k_sre_rowpass_occ(RowPassArgs A) {
+  using Sh = RowShape<T, NT, RB, NL, true>;
+  __shared__ typename Sh::Elem lds[Sh::LDS_N];
+  __shared__ double red[NT / 64 + 1];
+  rowpass_tiles<T, NT, RB, NL, false, QM, true>(A, blockIdx.x, gridDim.x, lds, red);
+}
+
 // ------------------------------------------------------------------------------------------------
 // Column pass
 // ------------------------------------------------------------------------------------------------
@@ -375,9 +385,32 @@ static int64_t row_tiles(const RowPassArgs &A) {
 }
 
 // Workgroup-resident row pass (one row = one whole folded shift vector of 2^NL values).
+template <typename T, int NT, int RB, int NL, int MINW>
+static void launch_row_occ(const RowPassArgs &A, bool q2, hipStream_t st) {
+  const dim3 grid((unsigned)grid_for(A.n_tiles)), block(NT);
+  ProfScope prof("sre_rowpass_resident", st);
+  if (q2) hipLaunchKernelGGL((k_sre_rowpass_occ<T, NT, RB, NL, 2, MINW>), grid, block, 0, st, A);
+  else hipLaunchKernelGGL((k_sre_rowpass_occ<T, NT, RB, NL, 0, (MINW > 3 ? 3 : MINW)>), grid, block, 0, st, A);  // general q: more accumulators
+}
+
+// split: tiles of 2^10..2^14 (FP32) / 2^10..2^13 (FP64) values use split LDS staging and a register
+// budget of 3 waves per SIMD (4 for 2^14 FP32 values: 512 threads x 32 values in 128 registers).
 template <typename T>
-static int launch_resident(int NL, RowPassArgs A, bool q2, hipStream_t st) {
+static int launch_resident(int NL, RowPassArgs A, bool q2, hipStream_t st, bool split = false) {
   constexpr int RB = ResidentRB<T>::value;
+  if (split && NL >= 10 && NL <= 14) {
+#define HM_RO(nl, nt, w)                                            \
+  case nl:                                                          \
+    A.n_tiles = row_tiles<nt, RB, nl>(A);                           \
+    launch_row_occ<T, nt, RB, nl, w>(A, q2, st);                    \
+    return OK;
+    if constexpr (RB == 5) {
+      switch (NL) { HM_RO(10, 128, 3) HM_RO(11, 128, 3) HM_RO(12, 128, 3) HM_RO(13, 256, 3) HM_RO(14, 512, 4) default: break; }
+    } else {
+      switch (NL) { HM_RO(10, 128, 3) HM_RO(11, 128, 3) HM_RO(12, 256, 3) HM_RO(13, 512, 3) default: break; }
+    }
+#undef HM_RO
+  }
 #define HM_RS(nl)                                                   \
   case nl:                                                          \
     A.n_tiles = row_tiles<64, nl, nl>(A);                           \
@@ -508,7 +541,7 @@ int shift_sums_t(const SrePlan &p, const void *psi, const QArgs &qa, uint64_t a0
     A.shift_sums = shift_sums;
     A.nacc = nacc;
     A.qa = qa;
-    int e = launch_resident<T>(p.nf, A, q2, st);
+    int e = launch_resident<T>(p.nf, A, q2, st, p.split != 0);
     if (e) return e;
     return hipPeekAtLastError() == hipSuccess ? OK : fail(E_HIP, "SRE row pass launch: %s", hipGetErrorString(hipGetLastError()));
   }
@@ -757,7 +790,7 @@ int states_t(const SrePlan &p, const void *const *psis, int n_states, const QArg
   A.n_states = n_states;
   A.state_bits = p.N;
   for (int i = 0; i < n_states; ++i) A.psis[i] = psis[i];
-  int e = launch_resident<T>(p.nf, A, is_q2(qa), st);
+  int e = launch_resident<T>(p.nf, A, is_q2(qa), st, p.split != 0);
   if (e) return e;
   return hipPeekAtLastError() == hipSuccess ? OK : fail(E_HIP, "SRE batched launch: %s", hipGetErrorString(hipGetLastError()));
 }

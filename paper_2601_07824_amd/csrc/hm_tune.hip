@@ -57,6 +57,9 @@ static std::vector<PlanOpts> candidates(const hm_context *h, int n, int dbl) {
   };
   PlanOpts r{};
   r.force_path = 1;
+  r.lds_split = 2;  // resident tiles with split staging and a higher occupancy budget
+  add(r);
+  r.lds_split = 1;
   add(r);
   const int nf = n - 1;
   const size_t per_shift = ((size_t)1 << nf) * (dbl ? 16 : 8);

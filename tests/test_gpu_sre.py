@@ -201,6 +201,23 @@ def test_vgpr_resident_large_tiles(orc, hm, c64, n):
     assert abs(m[0] - k * math.log2(4 / 3)) < (1e-9 if not c64 else 1e-5)
 
 
+@pytest.mark.parametrize("c64,n", [(True, 11), (True, 13), (True, 14), (True, 15), (False, 11), (False, 12), (False, 14)])
+def test_resident_split_staging(orc, hm, c64, n):
+    """Workgroup-resident tiles of 2^10..2^14 values with split LDS staging and the raised
+    occupancy register budget, against the oracle (single state and a batch of three)."""
+    ctx = hm.Context()
+    ctx.force_path(1)
+    ctx.set_option(hm.OPT_LDS_SPLIT, 2)
+    psi = S.gaussian_state(n, seed=3170 + n)
+    x, w = gpu_state(psi, c64)
+    say(f"[sre resident split] n={n} c64={c64}")
+    got = hm.sre(x, (1.0, 2.0, 3.0), ctx=ctx).cpu().numpy()
+    want = orc.sre_fwht(w, (1.0, 2.0, 3.0))
+    assert rel_err(got[:-1], want[:-1]) < TOL[c64], (got, want)
+    got = hm.sre_batched([x, x, x], (2.0,), ctx=ctx).cpu().numpy()
+    assert rel_err(got[:, 0], np.full(3, want[1])) < TOL[c64], (got, want)
+
+
 @pytest.mark.parametrize("c64", [False, True])
 def test_workgroup_resident_largest(orc, hm, c64):
     n = 13 if c64 else 12
