@@ -168,8 +168,13 @@ __device__ __forceinline__ void rowpass_tiles(const RowPassArgs &A, int64_t t0, 
   }
 }
 
+// Split-staged FP32 row-pass tiles keep to a register budget of four waves per SIMD (the column
+// pass would spill under it).
+template <typename T, bool SPLIT>
+struct TwoPassWaves { static constexpr int value = (SPLIT && sizeof(T) == 4) ? 4 : 1; };
+
 template <typename T, int NT, int RB, int NL, bool WRITE, int QM, bool SPLIT = false>
-__global__ __launch_bounds__(NT) void k_sre_rowpass(RowPassArgs A) {
+__global__ __launch_bounds__(NT, (WRITE ? TwoPassWaves<T, SPLIT>::value : 1)) void k_sre_rowpass(RowPassArgs A) {
   using Sh = RowShape<T, NT, RB, NL, SPLIT>;
   __shared__ typename Sh::Elem lds[Sh::LDS_N];
   __shared__ double red[NT / 64 + 1];
