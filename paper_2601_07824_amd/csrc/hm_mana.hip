@@ -12,6 +12,8 @@
 // positions [S, S+RT) of the row index, the thread's own index fills the other trits.  Strides in
 // LDS are odd multiples of the element size, so no padding is needed against bank conflicts.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 #include <math.h>
 #include <stdint.h>
 
@@ -120,6 +122,35 @@ __device__ __forceinline__ void relayout3(T (&re)[pow3c(RT)], T (&im)[pow3c(RT)]
   }
 }
 
+// The same, one component at a time through a scalar LDS buffer (half the LDS per workgroup).
+template <typename T, int RT, int SA, int SB, int ROWLEN>
+__device__ __forceinline__ void relayout3_one(T (&v)[pow3c(RT)], T *lds, uint32_t g, uint32_t tp, bool act) {
+  constexpr int R = pow3c(RT);
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) lds[g * ROWLEN + lay3<RT, SA>(tp, (uint32_t)r)] = v[r];
+  }
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = lds[g * ROWLEN + lay3<RT, SB>(tp, (uint32_t)r)];
+  }
+}
+template <typename T, int RT, int SA, int SB, int ROWLEN>
+__device__ __forceinline__ void relayout3_split(T (&re)[pow3c(RT)], T (&im)[pow3c(RT)], T *lds, uint32_t g,
+                                                uint32_t tp, bool act) {
+  relayout3_one<T, RT, SA, SB, ROWLEN>(re, lds, g, tp, act);
+  relayout3_one<T, RT, SA, SB, ROWLEN>(im, lds, g, tp, act);
+}
+// Complex or split staging by a compile-time switch.
+template <typename T, int RT, int SA, int SB, int ROWLEN, bool SPLIT, typename E>
+__device__ __forceinline__ void relayout3_any(T (&re)[pow3c(RT)], T (&im)[pow3c(RT)], E *lds, uint32_t g, uint32_t tp,
+                                              bool act) {
+  if constexpr (SPLIT) relayout3_split<T, RT, SA, SB, ROWLEN>(re, im, lds, g, tp, act);
+  else relayout3<T, RT, SA, SB, ROWLEN>(re, im, lds, g, tp, act);
+}
+
 // Block-wide FP64 sum of three per-thread values into acc[blockIdx] (added to what is there).
 template <int NT>
 __device__ __forceinline__ void block_acc3(double v0, double v1, double v2, double *red, double *acc, uint32_t tau) {
@@ -134,8 +165,10 @@ __device__ __forceinline__ void block_acc3(double v0, double v1, double v2, doub
   }
 }
 
+// Two-pass row tiles (WRITE) stage through LDS one component at a time.
 template <typename T, int NT, int RT, int NL, bool WRITE>
 __global__ __launch_bounds__(NT) void k_mana_rowpass(ManaRowArgs A) {
+  constexpr bool SPLIT = WRITE;
   constexpr int R = pow3c(RT);
   constexpr int ROWLEN = pow3c(NL);
   constexpr int TPR = pow3c(NL - RT);         // threads per row
@@ -146,7 +179,7 @@ __global__ __launch_bounds__(NT) void k_mana_rowpass(ManaRowArgs A) {
   static_assert(K <= 4, "at most four rounds");
   constexpr int LDS_N = K > 1 ? G * ROWLEN : 1;
 
-  __shared__ vec2<T> lds[LDS_N];
+  __shared__ typename std::conditional<SPLIT, T, vec2<T>>::type lds[LDS_N];
   __shared__ double red[3 * (NT / 64 + 1)];
 
   const vec2<T> *__restrict__ psi = (const vec2<T> *)A.psi;
@@ -229,15 +262,15 @@ __global__ __launch_bounds__(NT) void k_mana_rowpass(ManaRowArgs A) {
     }
     if constexpr (K >= 1) f3_regs<T, RT, 0, mr_H(NL, RT, 0)>(re, im);
     if constexpr (K >= 2) {
-      relayout3<T, RT, mr_S(NL, RT, 0), mr_S(NL, RT, 1), ROWLEN>(re, im, lds, g, tp, tact);
+      relayout3_any<T, RT, mr_S(NL, RT, 0), mr_S(NL, RT, 1), ROWLEN, SPLIT>(re, im, lds, g, tp, tact);
       f3_regs<T, RT, 0, mr_H(NL, RT, 1)>(re, im);
     }
     if constexpr (K >= 3) {
-      relayout3<T, RT, mr_S(NL, RT, 1), mr_S(NL, RT, 2), ROWLEN>(re, im, lds, g, tp, tact);
+      relayout3_any<T, RT, mr_S(NL, RT, 1), mr_S(NL, RT, 2), ROWLEN, SPLIT>(re, im, lds, g, tp, tact);
       f3_regs<T, RT, 0, mr_H(NL, RT, 2)>(re, im);
     }
     if constexpr (K >= 4) {
-      relayout3<T, RT, mr_S(NL, RT, 2), mr_S(NL, RT, 3), ROWLEN>(re, im, lds, g, tp, tact);
+      relayout3_any<T, RT, mr_S(NL, RT, 2), mr_S(NL, RT, 3), ROWLEN, SPLIT>(re, im, lds, g, tp, tact);
       f3_regs<T, RT, 0, mr_H(NL, RT, 3)>(re, im);
     }
     if constexpr (WRITE) {
@@ -290,6 +323,7 @@ __host__ __device__ constexpr int mc_H(int NH, int RT, int CT, int k) {
 template <int RT, int S>
 __device__ __forceinline__ uint32_t lay3t(uint32_t tau, uint32_t rho) { return lay3<RT, S>(tau, rho); }
 
+// Column tiles stage through LDS one component at a time (half the LDS, more workgroups per CU).
 template <typename T, int NT, int RT, int NH, int CT>
 __global__ __launch_bounds__(NT) void k_mana_colpass(ManaColArgs A) {
   constexpr int R = pow3c(RT);
@@ -301,7 +335,7 @@ __global__ __launch_bounds__(NT) void k_mana_colpass(ManaColArgs A) {
   static_assert(K <= 4, "at most four rounds");
   constexpr int LDS_N = K > 1 ? TILE : 1;
 
-  __shared__ vec2<T> lds[LDS_N];
+  __shared__ T lds[LDS_N];
   __shared__ double red[3 * (NT / 64 + 1)];
 
   const vec2<T> *__restrict__ ex = (const vec2<T> *)A.exch;
@@ -331,15 +365,15 @@ __global__ __launch_bounds__(NT) void k_mana_colpass(ManaColArgs A) {
     }
     f3_regs<T, RT, mc_L(NH, RT, CT, 0), mc_H(NH, RT, CT, 0)>(re, im);
     if constexpr (K >= 2) {
-      relayout3<T, RT, mc_S(NH, RT, CT, 0), mc_S(NH, RT, CT, 1), 0>(re, im, lds, 0, tau, tact);
+      relayout3_split<T, RT, mc_S(NH, RT, CT, 0), mc_S(NH, RT, CT, 1), 0>(re, im, lds, 0, tau, tact);
       f3_regs<T, RT, mc_L(NH, RT, CT, 1), mc_H(NH, RT, CT, 1)>(re, im);
     }
     if constexpr (K >= 3) {
-      relayout3<T, RT, mc_S(NH, RT, CT, 1), mc_S(NH, RT, CT, 2), 0>(re, im, lds, 0, tau, tact);
+      relayout3_split<T, RT, mc_S(NH, RT, CT, 1), mc_S(NH, RT, CT, 2), 0>(re, im, lds, 0, tau, tact);
       f3_regs<T, RT, mc_L(NH, RT, CT, 2), mc_H(NH, RT, CT, 2)>(re, im);
     }
     if constexpr (K >= 4) {
-      relayout3<T, RT, mc_S(NH, RT, CT, 2), mc_S(NH, RT, CT, 3), 0>(re, im, lds, 0, tau, tact);
+      relayout3_split<T, RT, mc_S(NH, RT, CT, 2), mc_S(NH, RT, CT, 3), 0>(re, im, lds, 0, tau, tact);
       f3_regs<T, RT, mc_L(NH, RT, CT, 3), mc_H(NH, RT, CT, 3)>(re, im);
     }
     if (tact) {
@@ -424,9 +458,9 @@ static int mana_plan(int N, int dbl, int64_t batch, ManaPlan *p) {
     P.nl = nl;
     P.nh = nh;
     const size_t per_pair = (size_t)pow3c(N) * (dbl ? 16 : 8);
-    // Untuned: 512 MiB (FP32) / 256 MiB (FP64) of exchange per launch pair, measured faster than
-    // 128 MiB at n = 12 on MI355X (fewer launches outweigh leaving the memory-side cache).
-    int64_t b = batch > 0 ? (batch + 1) / 2 : (int64_t)(((dbl ? 256ull : 512ull) << 20) / per_pair);
+    // Untuned: 192 MiB of exchange per launch pair, inside the 256 MiB memory-side cache (at n = 12
+    // on MI355X: 0.66 s against 0.68 s at 256 MiB and 0.77-0.79 s at 512 MiB - 1 GiB).
+    int64_t b = batch > 0 ? (batch + 1) / 2 : (int64_t)((192ull << 20) / per_pair);
     if ((size_t)b * per_pair > (3ull << 30)) b = (int64_t)((3ull << 30) / per_pair);  // 32-bit offsets
     if (b < 1) b = 1;
     P.batch_pairs = (int)b;
