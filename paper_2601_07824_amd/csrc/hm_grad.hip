@@ -235,9 +235,16 @@ static int grad2_plan(const PlanOpts &o, int N, int dbl, SrePlan *p) {
   g.force_path = 2;
   g.pipeline = 1;
   g.batch = o.batch;
+  g.row_rb = 4;  // 2^4-value row tiles on the row side (forward, backward, fused accumulation)
   int e = sre_plan(N, dbl, g, p);
   if (e) return e;
   if (p->nf < 11 || p->nf > 19) return fail(E_UNSUPPORTED, "gradient: two-pass kernels cover n in [12, 20] (n = %d)", N);
+  // Batches of at most 2^nl aligned shifts: every batch after the first then shares its top bit and
+  // its bits above nl, which the fused backward-row + accumulation kernel needs.
+  if (!o.batch && p->batch > (1 << p->nl)) {
+    g.batch = (int64_t)1 << p->nl;
+    if ((e = sre_plan(N, dbl, g, p))) return e;
+  }
   return OK;
 }
 

@@ -86,6 +86,155 @@ __global__ __launch_bounds__(NT) void k_sre_rowback(RowPassArgs A) {
   }
 }
 
+// ---- fused backward row pass + accumulation ------------------------------------------------------
+// For a batch whose shifts a share their top bit j (and, when j >= NL, their bits above NL), row ch
+// of the folded vector maps, for every shift of the batch, onto the same two sets of gradient
+// entries: the x side y = x(c) (bit j clear) and the partner side y = x(c) ^ a (bit j set), with
+// the partner's position inside its block permuted by the shift's low bits.  One workgroup takes one
+// row for a group of the batch's shifts (G shifts at a time, one per row task), runs the backward row
+// stages, and accumulates the x side in registers and the partner side in per-row-task LDS slices;
+// the slices are then summed in fixed order and added to the group's FP64 partial of G.  Rows own
+// disjoint entries, so there are no atomics and the result is deterministic.
+struct FusedArgs {
+  const void *psi;
+  const void *exch;   // adjoint rows after the column pass, row-pass output layout
+  int nf, nh;
+  int64_t n_slots;
+  uint64_t a0;
+  double q;
+  int j;              // common top bit of the batch's shifts
+  uint32_t ah;        // common a >> NL (used when j >= NL)
+  double2 *gpart;     // [groups][2^N]
+  int groups;
+};
+
+template <typename T, int NT, int RB, int NL, bool SPLIT>
+__global__ __launch_bounds__(NT) void k_grad_rowback_accum(FusedArgs F) {
+  using Sh = RowShape<T, NT, RB, NL, SPLIT>;
+  constexpr int R = 1 << RB;
+  constexpr int LT = ilog2c(NT);
+  constexpr int TB = LT + RB;
+  static_assert(TB >= NL && NL >= RB, "tile must hold whole rows");
+  constexpr int S0 = NL - RB;
+  constexpr int K = (NL + RB - 1) / RB;
+  static_assert(K >= 2 && K <= 4, "two to four rounds");
+  constexpr int SEG = 1 << S0;       // threads per row task
+  constexpr int G = 1 << (TB - NL);  // row tasks (shifts in flight) per workgroup
+  constexpr int ROW = 1 << NL;
+  __shared__ typename Sh::Elem lds[Sh::LDS_N];
+  __shared__ vec2<T> slice[G * ROW];
+
+  const vec2<T> *__restrict__ ex = (const vec2<T> *)F.exch;
+  const vec2<T> *__restrict__ psi = (const vec2<T> *)F.psi;
+  const uint32_t tau = threadIdx.x;
+  const uint32_t tlo = tau & (SEG - 1);
+  const uint32_t g = tau >> S0;
+  const int64_t nrows = (int64_t)1 << F.nh;
+  const uint32_t ch = (uint32_t)((int64_t)blockIdx.x % nrows);
+  const int grp = (int)((int64_t)blockIdx.x / nrows);
+  const int64_t per = (F.n_slots + F.groups - 1) / F.groups;
+  const int64_t s_lo = (int64_t)grp * per;
+  const int64_t s_hi = (s_lo + per) < F.n_slots ? (s_lo + per) : F.n_slots;
+  const int j = F.j;
+  const bool jhi = j >= NL;
+  // x side: y = x(c) for c = ch * ROW + p; partner block origin
+  const uint32_t xh = jhi ? (uint32_t)ins0_32(ch, j - NL) : 0u;
+  const T q4 = (T)(4.0 * F.q);
+
+  for (uint32_t i = tau; i < (uint32_t)(G * ROW); i += NT) slice[i] = vec2<T>{T(0), T(0)};
+  T axr[R], axi[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) axr[r] = axi[r] = T(0);
+
+  for (int64_t sb = s_lo; sb < s_hi; sb += G) {
+    const int64_t s = sb + g;
+    const bool active = s < s_hi;
+    const uint32_t ob = ((((uint32_t)s << F.nh) + ch) << NL) | tlo;
+    T re[R], im[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      vec2<T> v{T(0), T(0)};
+      if (active) v = ld32(ex, ob + ((uint32_t)r << S0));
+      re[r] = v.x;
+      im[r] = v.y;
+    }
+    if constexpr (K >= 4) {
+      wht_regs<T, R, 0, rp_H(NL, RB, 3)>(re, im);
+      if constexpr (SPLIT) relayout_split<T, R, RB, rp_S(NL, RB, 3), rp_S(NL, RB, 2)>(re, im, lds, tau);
+      else relayout<T, R, RB, rp_S(NL, RB, 3), rp_S(NL, RB, 2)>(re, im, lds, tau);
+    }
+    if constexpr (K >= 3) {
+      wht_regs<T, R, 0, rp_H(NL, RB, 2)>(re, im);
+      if constexpr (SPLIT) relayout_split<T, R, RB, rp_S(NL, RB, 2), rp_S(NL, RB, 1)>(re, im, lds, tau);
+      else relayout<T, R, RB, rp_S(NL, RB, 2), rp_S(NL, RB, 1)>(re, im, lds, tau);
+    }
+    wht_regs<T, R, 0, rp_H(NL, RB, 1)>(re, im);
+    if constexpr (SPLIT) relayout_split<T, R, RB, rp_S(NL, RB, 1), rp_S(NL, RB, 0)>(re, im, lds, tau);
+    else relayout<T, R, RB, rp_S(NL, RB, 1), rp_S(NL, RB, 0)>(re, im, lds, tau);
+    wht_regs<T, R, 0, rp_H(NL, RB, 0)>(re, im);
+    if (active) {
+      const uint32_t a = (uint32_t)(F.a0 + (uint64_t)s);
+      const uint32_t m = jhi ? (a & (uint32_t)(ROW - 1)) : (a & ((1u << j) - 1u));  // partner position = p ^ m
+      vec2<T> *sl = slice + g * ROW;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const uint32_t p = tlo + ((uint32_t)r << S0);
+        const uint32_t x = jhi ? ((xh << NL) | p) : ((ch << (NL + 1)) | ins0_32(p, j));
+        const uint32_t xp = x ^ a;
+        const vec2<T> py = ld32(psi, xp), px = ld32(psi, x);
+        const T zr = q4 * re[r], zi = q4 * im[r];
+        // G_x += 4q psi_{x^a} Z ;  G_{x^a} += 4q psi_x conj(Z)
+        axr[r] += fmaT(py.x, zr, -(py.y * zi));
+        axi[r] += fmaT(py.x, zi, py.y * zr);
+        vec2<T> o = sl[p ^ m];
+        o.x += fmaT(px.x, zr, px.y * zi);
+        o.y += fmaT(px.y, zr, -(px.x * zi));
+        sl[p ^ m] = o;
+        if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // keep the state gathers in groups of four
+      }
+    }
+  }
+  if (s_lo >= s_hi) return;  // uniform: no shifts in this group
+  double2 *gp = F.gpart + ((size_t)grp << (F.nf + 1));
+  const uint32_t ah_sh = jhi ? ((xh ^ F.ah) << NL) : 0u;
+  __syncthreads();
+  // partner side: fixed-order sum over the row tasks' slices
+  for (uint32_t p = tau; p < (uint32_t)ROW; p += NT) {
+    double sr = 0.0, si = 0.0;
+    for (int k = 0; k < G; ++k) {
+      const vec2<T> v = slice[k * ROW + p];
+      sr += (double)v.x;
+      si += (double)v.y;
+    }
+    const uint32_t y = jhi ? (ah_sh | p) : ((ch << (NL + 1)) | ins0_32(p, j) | (1u << j));
+    double2 o = gp[y];
+    o.x += sr;
+    o.y += si;
+    gp[y] = o;
+  }
+  __syncthreads();
+  // x side: registers through the slices, then the same fixed-order sum
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t p = tlo + ((uint32_t)r << S0);
+    slice[g * ROW + p] = vec2<T>{axr[r], axi[r]};
+  }
+  __syncthreads();
+  for (uint32_t p = tau; p < (uint32_t)ROW; p += NT) {
+    double sr = 0.0, si = 0.0;
+    for (int k = 0; k < G; ++k) {
+      const vec2<T> v = slice[k * ROW + p];
+      sr += (double)v.x;
+      si += (double)v.y;
+    }
+    const uint32_t y = jhi ? ((xh << NL) | p) : ((ch << (NL + 1)) | ins0_32(p, j));
+    double2 o = gp[y];
+    o.x += sr;
+    o.y += si;
+    gp[y] = o;
+  }
+}
+
 struct AccumArgs {
   const void *psi;
   const void *z;       // [n_slots][2^nf] adjoint values in natural folded order
@@ -181,7 +330,7 @@ __global__ void k_zero2(double2 *p, int64_t n) {
 
 // ---- launchers (default two-pass split only) -----------------------------------------------------
 template <typename T, int RB, int NF, bool SPLIT>
-static void grad2_launch_nf(int step, RowPassArgs &A, ColPassArgs &C, bool q2, hipStream_t st) {
+static void grad2_launch_nf(int step, RowPassArgs &A, ColPassArgs &C, const FusedArgs *F, bool q2, hipStream_t st) {
   constexpr int TB = sre_default_col_tb(NF, sizeof(T) == 8, RB);
   constexpr int NL = sre_default_nl(NF, TB, RB);
   constexpr int NH = NF - NL;
@@ -197,22 +346,33 @@ static void grad2_launch_nf(int step, RowPassArgs &A, ColPassArgs &C, bool q2, h
     ProfScope prof("sre_grad_colpass", st);
     if (q2) hipLaunchKernelGGL((k_sre_colpass_adj<T, NTC, RBC, NH, CB, 2, SPLIT>), grid, block, 0, st, C);
     else hipLaunchKernelGGL((k_sre_colpass_adj<T, NTC, RBC, NH, CB, 0, SPLIT>), grid, block, 0, st, C);
-  } else {
+  } else if (step == 3) {
+    // row tiles of 2^4 values per thread on the row side of the gradient (the plan's row_rb)
+    constexpr int RBR = 4;
     constexpr int TBR = NL > 12 ? 13 : 12;
-    constexpr int NTR = 1 << (TBR - RB);
-    A.n_tiles = row_tiles<NTR, RB, NL>(A);
+    constexpr int NTR = 1 << (TBR - RBR);
+    A.n_tiles = row_tiles<NTR, RBR, NL>(A);
     const dim3 grid((unsigned)grid_for(A.n_tiles)), block(NTR);
     ProfScope prof("sre_grad_rowback", st);
-    hipLaunchKernelGGL((k_sre_rowback<T, NTR, RB, NL, SPLIT>), grid, block, 0, st, A);
+    hipLaunchKernelGGL((k_sre_rowback<T, NTR, RBR, NL, SPLIT>), grid, block, 0, st, A);
+  } else {
+    // fused backward rows + accumulation: 128 threads x 2^4 values, 2^(11 - NL) shifts in flight
+    constexpr int RBR = 4;
+    constexpr int NTF = 128;
+    static_assert(ilog2c(NTF) + RBR >= NL, "fused tile must hold a whole row");
+    const dim3 grid((unsigned)(((int64_t)1 << F->nh) * F->groups)), block(NTF);
+    ProfScope prof("sre_grad_rowback_accum", st);
+    hipLaunchKernelGGL((k_grad_rowback_accum<T, NTF, RBR, NL, SPLIT>), grid, block, 0, st, *F);
   }
 }
 
 template <typename T, bool SPLIT>
-static int grad2_launch(int nf, int step, RowPassArgs &A, ColPassArgs &C, bool q2, hipStream_t st) {
+static int grad2_launch(int nf, int step, RowPassArgs &A, ColPassArgs &C, const FusedArgs *F, bool q2,
+                        hipStream_t st) {
   constexpr int RB = ResidentRB<T>::value;
 #define HM_G2(nf_)                                                  \
   case nf_:                                                         \
-    grad2_launch_nf<T, RB, nf_, SPLIT>(step, A, C, q2, st);         \
+    grad2_launch_nf<T, RB, nf_, SPLIT>(step, A, C, F, q2, st);      \
     return OK;
   switch (nf) {
     HM_G2(11) HM_G2(12) HM_G2(13) HM_G2(14) HM_G2(15) HM_G2(16) HM_G2(17) HM_G2(18) HM_G2(19)
@@ -289,9 +449,38 @@ int grad2_t(const SrePlan &p, const void *psi, double q, double *out, void *grad
     C.prev_n_slots = prev_nb;
     C.prev_a0 = (uint64_t)prev_s0;
     C.prev_shift_sums = shift_sums + prev_s0 * nacc;
-    e = p.split ? grad2_launch<T, true>(nf, 2, A, C, q2, st) : grad2_launch<T, false>(nf, 2, A, C, q2, st);
+    e = p.split ? grad2_launch<T, true>(nf, 2, A, C, nullptr, q2, st)
+                : grad2_launch<T, false>(nf, 2, A, C, nullptr, q2, st);
     if (e) return e;
-    e = p.split ? grad2_launch<T, true>(nf, 3, A, C, q2, st) : grad2_launch<T, false>(nf, 3, A, C, q2, st);
+    // Fused backward rows + accumulation when every shift of the batch has the same top bit j and,
+    // for j >= nl, the same bits above nl (so each row owns fixed gradient entries).
+    const uint64_t a_first = (uint64_t)s0, a_last = (uint64_t)(s0 + nb - 1);
+    const int j0 = a_first ? 63 - __builtin_clzll(a_first) : -1;
+    const int j1 = 63 - __builtin_clzll(a_last | 1);
+    const bool fuse = a_first != 0 && j0 == j1 && (j0 < p.nl || (a_first >> p.nl) == (a_last >> p.nl));
+    if (fuse) {
+      FusedArgs F{};
+      F.psi = psi;
+      F.exch = exch;
+      F.nf = nf;
+      F.nh = p.nh;
+      F.n_slots = nb;
+      F.a0 = a_first;
+      F.q = q;
+      F.j = j0;
+      F.ah = (uint32_t)(a_first >> p.nl);
+      F.gpart = gpart;
+      // shift groups: at least one round of the 2^(11 - nl) shifts a workgroup holds at a time
+      const int64_t gf = nb >> (11 - p.nl);
+      F.groups = (int)(gf < 1 ? 1 : gf < groups ? gf : groups);
+      e = p.split ? grad2_launch<T, true>(nf, 4, A, C, &F, q2, st) : grad2_launch<T, false>(nf, 4, A, C, &F, q2, st);
+      if (e) return e;
+      prev_s0 = s0;
+      prev_nb = nb;
+      continue;
+    }
+    e = p.split ? grad2_launch<T, true>(nf, 3, A, C, nullptr, q2, st)
+                : grad2_launch<T, false>(nf, 3, A, C, nullptr, q2, st);
     if (e) return e;
     AccumArgs G{};
     G.psi = psi;

@@ -134,17 +134,22 @@ def test_grad_determinism(hm):
 
 
 # ---- two-pass gradient (row pass, adjoint column pass, backward row pass, accumulation) ----------
+@pytest.mark.parametrize("batch", [96, 0])
 @pytest.mark.parametrize("c64,n,forced", [(False, 12, True), (True, 12, True), (True, 13, True), (False, 13, False),
                                           (True, 14, False), (False, 14, False)])
-def test_grad_two_pass_vs_fwht_oracle(orc, hm, c64, n, forced):
+def test_grad_two_pass_vs_fwht_oracle(orc, hm, c64, n, forced, batch):
+    """batch 96: unaligned batches (backward row pass and accumulation as separate kernels, last batch
+    ragged); default batches (aligned, 2^nl shifts: the fused backward-row + accumulation kernel for
+    every batch after the first)."""
     psi = S.ry_rz_cz_state(n, np.random.default_rng(6600 + n).uniform(0, 2 * math.pi, (2, 2, n)))
     x, w = gpu_state(psi, c64)
     ctx = hm.Context()
     if forced:
         ctx.force_path(2)
-    ctx.batch_shifts(96)  # several batches, the last one ragged
+    if batch:
+        ctx.batch_shifts(batch)
     for q in ((2.0, 3.0) if n <= 13 else (2.0,)):
-        say(f"[grad two-pass] n={n} c64={c64} forced={forced} q={q}")
+        say(f"[grad two-pass] n={n} c64={c64} forced={forced} batch={batch} q={q}")
         out, g = hm.sre_grad(x, q, ctx=ctx)
         want_out, want_g = orc.sre_grad_fwht(w, q)
         err = rel_l2(g.cpu().numpy().astype(np.complex128), want_g)
