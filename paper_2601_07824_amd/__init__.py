@@ -194,9 +194,15 @@ def workspace_size(op: int, n: int, dtype_code: int, n_q: int = 1, count: int = 
     return b.value
 
 
-def _workspace(nbytes: int, device):
+def _workspace(nbytes: int, device, stream=None):
+    """Scratch for one call.  Allocated through torch's caching allocator on the current stream; when
+    the call runs on another stream the block is marked as used there, so the allocator does not hand
+    it out again before that stream is done with it."""
     torch = _torch()
-    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+    ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+    if stream is not None and stream != torch.cuda.current_stream(device):
+        ws.record_stream(stream)
+    return ws
 
 
 def profile_enable(on: bool | int = True):
@@ -236,7 +242,7 @@ def sre(psi, q: Sequence[float] | float = (2.0,), *, ctx: Context | None = None,
     psi, n = _state(psi, 2)
     qa, nq = _q(q)
     dt = _dtype_code(psi)
-    ws = _workspace(workspace_size(OP_SRE, n, dt, nq, 0, ctx), psi.device)
+    ws = _workspace(workspace_size(OP_SRE, n, dt, nq, 0, ctx), psi.device, stream)
     out = torch.empty(nq + 1, dtype=torch.float64, device=psi.device)
     _check(lib().hm_sre(ctx.h, _ptr(psi), n, dt, qa, nq, _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
     return out
@@ -250,7 +256,7 @@ def sre_partial(psi, q=(2.0,), a0: int = 0, a1: int | None = None, *, ctx: Conte
     a1 = (1 << n) if a1 is None else a1
     qa, nq = _q(q)
     dt = _dtype_code(psi)
-    ws = _workspace(workspace_size(OP_SRE, n, dt, nq, 0, ctx), psi.device)
+    ws = _workspace(workspace_size(OP_SRE, n, dt, nq, 0, ctx), psi.device, stream)
     out = torch.empty(nq + 1, dtype=torch.float64, device=psi.device)
     _check(lib().hm_sre_partial(ctx.h, _ptr(psi), n, dt, qa, nq, a0, a1, _ptr(out), _ptr(ws), ws.numel(),
                                 _stream(stream)))
@@ -278,7 +284,7 @@ def sre_rows(psi, rows, q=(2.0,), *, ctx: Context | None = None, stream=None):
     rows = rows.to(device=psi.device, dtype=torch.int64).contiguous()
     nr = rows.numel()
     out = torch.empty((nr, nq + 1), dtype=torch.float64, device=psi.device)
-    ws = _workspace(workspace_size(OP_SRE_ROWS, n, dt, nq, nr, ctx), psi.device)
+    ws = _workspace(workspace_size(OP_SRE_ROWS, n, dt, nq, nr, ctx), psi.device, stream)
     _check(lib().hm_sre_rows(ctx.h, _ptr(psi), n, dt, _ptr(rows), nr, qa, nq, _ptr(out), _ptr(ws), ws.numel(),
                              _stream(stream)))
     return out
@@ -295,7 +301,7 @@ def autotune(psi, sample_shifts: int = 16384, *, ctx: Context | None = None, str
     dt = _dtype_code(psi)
     b = _sz(0)
     _check(lib().hm_autotune_workspace(ctx.h, n, dt, sample_shifts, ctypes.byref(b)))
-    ws = _workspace(b.value, psi.device)
+    ws = _workspace(b.value, psi.device, stream)
     _check(lib().hm_autotune(ctx.h, _ptr(psi), n, dt, sample_shifts, _ptr(ws), ws.numel(), _stream(stream)))
     return tuned_plan(n, dt, ctx=ctx)
 
@@ -332,7 +338,7 @@ def sre_batched(states, q=(2.0,), *, ctx: Context | None = None, stream=None):
     ptrs = (_vp * B)(*[s.data_ptr() for s in sts])
     b = _sz(0)
     _check(lib().hm_sre_batched_workspace(ctx.h, ns_c, B, dt, nq, ctypes.byref(b)))
-    ws = _workspace(b.value, sts[0].device)
+    ws = _workspace(b.value, sts[0].device, stream)
     out = torch.empty((B, nq + 1), dtype=torch.float64, device=sts[0].device)
     _check(lib().hm_sre_batched(ctx.h, ptrs, ns_c, B, dt, qa, nq, _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
     out._hm_keepalive = (sts, ws)
@@ -351,7 +357,7 @@ def sre_sampled(psi, n_rows: int = 4096, seed: int = 0, rows=None, *, ctx: Conte
         rows = np.random.default_rng(seed).integers(1, 2 ** n, size=n_rows, dtype=np.uint64)
     rows = torch.as_tensor(np.asarray(rows, dtype=np.int64)).to(psi.device)
     out = torch.empty(4, dtype=torch.float64, device=psi.device)
-    ws = _workspace(workspace_size(OP_SRE_SAMPLED, n, dt, 1, rows.numel(), ctx), psi.device)
+    ws = _workspace(workspace_size(OP_SRE_SAMPLED, n, dt, 1, rows.numel(), ctx), psi.device, stream)
     _check(lib().hm_sre_sampled(ctx.h, _ptr(psi), n, dt, _ptr(rows), rows.numel(), _ptr(out), _ptr(ws), ws.numel(),
                                 _stream(stream)))
     return out
@@ -364,7 +370,7 @@ def sre_row_values(psi, a: int, *, ctx: Context | None = None, stream=None):
     psi, n = _state(psi, 2)
     dt = _dtype_code(psi)
     out = torch.empty(1 << n, dtype=torch.float64, device=psi.device)
-    ws = _workspace(workspace_size(OP_ROW_VALUES, n, dt, 1, 0, ctx), psi.device)
+    ws = _workspace(workspace_size(OP_ROW_VALUES, n, dt, 1, 0, ctx), psi.device, stream)
     _check(lib().hm_sre_row_values(ctx.h, _ptr(psi), n, dt, int(a), _ptr(out), _ptr(ws), ws.numel(),
                                    _stream(stream)))
     return out
@@ -378,7 +384,7 @@ def sre_grad(psi, q: float = 2.0, *, ctx: Context | None = None, stream=None):
     dt = _dtype_code(psi)
     out = torch.empty(2, dtype=torch.float64, device=psi.device)
     grad = torch.empty_like(psi)
-    ws = _workspace(workspace_size(OP_SRE_GRAD, n, dt, 1, 0, ctx), psi.device)
+    ws = _workspace(workspace_size(OP_SRE_GRAD, n, dt, 1, 0, ctx), psi.device, stream)
     _check(lib().hm_sre_grad(ctx.h, _ptr(psi), n, dt, float(q), _ptr(out), _ptr(grad), _ptr(ws), ws.numel(),
                              _stream(stream)))
     return out, grad
@@ -427,7 +433,7 @@ def mana(psi, *, ctx: Context | None = None, stream=None):
     psi, n = _state(psi, 3)
     dt = _dtype_code(psi)
     out = torch.empty(3, dtype=torch.float64, device=psi.device)
-    ws = _workspace(workspace_size(OP_MANA, n, dt, 1, 0, ctx), psi.device)
+    ws = _workspace(workspace_size(OP_MANA, n, dt, 1, 0, ctx), psi.device, stream)
     _check(lib().hm_mana(ctx.h, _ptr(psi), n, dt, _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
     return out
 
@@ -439,6 +445,6 @@ def mana_partial(psi, a0: int = 0, a1: int | None = None, *, ctx: Context | None
     a1 = 3 ** n if a1 is None else a1
     dt = _dtype_code(psi)
     out = torch.empty(3, dtype=torch.float64, device=psi.device)
-    ws = _workspace(workspace_size(OP_MANA, n, dt, 1, 0, ctx), psi.device)
+    ws = _workspace(workspace_size(OP_MANA, n, dt, 1, 0, ctx), psi.device, stream)
     _check(lib().hm_mana_partial(ctx.h, _ptr(psi), n, dt, a0, a1, _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
     return out
