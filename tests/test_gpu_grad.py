@@ -227,3 +227,18 @@ def test_grad_two_pass_deterministic(hm):
     a = hm.sre_grad(x, 2.0)[1].cpu().numpy()
     b = hm.sre_grad(x, 2.0)[1].cpu().numpy()
     assert np.array_equal(a, b)
+
+
+def test_grad_maximum_size_identities(hm):
+    """n = 20 (largest gradient size), complex64: homogeneity and phase invariance of the gradient
+    and M_2 against the forward entry point."""
+    n = 20
+    psi = S.ry_rz_cz_state(n, np.random.default_rng(6990).uniform(0, 2 * math.pi, (2, 2, n)))
+    x, _ = gpu_state(psi, True)
+    say("[grad max size] n=20 c64")
+    out, g = hm.sre_grad(x, 2.0)
+    ip = torch.vdot(g.to(torch.complex128), x.to(torch.complex128)).item()
+    want = 4 * 2.0 / ((1 - 2.0) * math.log(2))
+    assert abs(ip.real - want) < 1e-4 * abs(want) and abs(ip.imag) < 1e-4 * abs(want), ip
+    m = hm.sre(x, (2.0,)).cpu().numpy()
+    assert abs(out.cpu().numpy()[0] - m[0]) < 1e-5 * abs(m[0])

@@ -164,3 +164,19 @@ def test_determinism(hm):
     a = hm.mana(x).cpu().numpy()
     b = hm.mana(x).cpu().numpy()
     assert np.array_equal(a, b)
+
+
+def test_maximum_size_partial(orc, hm):
+    """n = 16 qutrits (3^16 complex64 values, 344 MB): sums over a few shift pairs (a0 = 0 and an
+    interior range, both ragged) against the oracle."""
+    n = 16
+    g = np.random.default_rng(5600)
+    psi = (g.standard_normal(3 ** n) + 1j * g.standard_normal(3 ** n)).astype(np.complex128)
+    psi /= np.linalg.norm(psi)
+    x, w = gpu_state(psi, True)
+    del psi
+    for a0, a1 in ((0, 3), (3 ** 15 + 1, 3 ** 15 + 4)):
+        say(f"[mana max size] n={n} [{a0},{a1})")
+        got = hm.mana_partial(x, a0, a1).cpu().numpy()
+        want = orc.mana_fft_sums(w, a0, a1)
+        np.testing.assert_allclose(got, want, rtol=2e-5, atol=1e-6)

@@ -377,3 +377,20 @@ def test_autotuned_plan_matches(orc, hm, c64, n):
     if n <= 14:
         want = orc.sre_fwht(w, (2.0,))
         assert rel_err(got[:-1], want[:-1]) < TOL[c64]
+
+
+@pytest.mark.parametrize("c64,n", [(True, 26), (False, 25)])
+def test_maximum_sizes_sampled_rows(orc, hm, c64, n):
+    """Largest supported states (complex64 n = 26: 512 MB; complex128 n = 25: 512 MB): per-row sums
+    of a few X-rows (both fold cases and the a = 0 row) against the oracle, in the launch
+    configuration the planner picks at that size."""
+    g = np.random.default_rng(4300 + n)
+    psi = (g.standard_normal(2 ** n) + 1j * g.standard_normal(2 ** n)).astype(np.complex128)
+    psi /= np.linalg.norm(psi)
+    x, w = gpu_state(psi, c64)
+    del psi
+    rows = np.array([0, 5, 2 ** (n - 1) + 3], dtype=np.int64)
+    say(f"[sre max size rows] n={n} c64={c64}")
+    got = hm.sre_rows(x, rows, (2.0,)).cpu().numpy()
+    want = orc.sre_rows(w, rows.astype(np.uint64), (2.0,))
+    assert rel_err(got, want, floor=1e-15) < (1e-5 if c64 else 1e-10), (got, want)
