@@ -21,6 +21,9 @@ def cases():
     # (key, builder, kind, q)
     yield ("sre_brickwall_n16_d32_seed4200_c64", lambda: S.to_c64_exact(S.brickwall_haar(16, 32, seed=4200))[1], "sre", [2.0])
     yield ("sre_gauss_n16_seed4201_c128", lambda: S.gaussian_state(16, seed=4201), "sre", [1.0, 2.0, 3.0])
+    for k in (1, 4, 16):
+        yield (f"sre_clifford_t_n16_k{k}_seed42{k:02d}_c64",
+               (lambda k=k: S.to_c64_exact(S.clifford_t_state(16, k, seed=4200 + k))[1]), "sre", [2.0])
     yield ("mana_gauss_n8_seed5008_c128", lambda: S.gaussian_state(8, d=3, seed=5008), "mana", None)
     yield ("mana_gauss_n10_seed5010_c64", lambda: S.to_c64_exact(S.gaussian_state(10, d=3, seed=5010))[1], "mana", None)
 

@@ -394,3 +394,18 @@ def test_maximum_sizes_sampled_rows(orc, hm, c64, n):
     got = hm.sre_rows(x, rows, (2.0,)).cpu().numpy()
     want = orc.sre_rows(w, rows.astype(np.uint64), (2.0,))
     assert rel_err(got, want, floor=1e-15) < (1e-5 if c64 else 1e-10), (got, want)
+
+
+@pytest.mark.parametrize("k", [1, 4, 16])
+def test_clifford_t_n16_vs_golden(hm, k):
+    """Random Clifford circuits with k T gates at seeded positions (n = 16), complex64 values and
+    the same values widened to complex128, against FP64 oracle values stored by
+    tests/golden/make_golden.py."""
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "oracle_golden.json")))
+    want = np.array(gold[f"sre_clifford_t_n16_k{k}_seed42{k:02d}_c64"]["values"])
+    v, w = S.to_c64_exact(S.clifford_t_state(16, k, seed=4200 + k))
+    for t, tol in ((torch.from_numpy(v), 1e-5), (torch.from_numpy(w), 1e-10)):
+        say(f"[sre clifford+T golden] k={k} dtype={t.dtype}")
+        got = hm.sre(t.to(_dev()), (2.0,)).cpu().numpy()
+        assert abs(got[0] - want[0]) < tol * max(1.0, abs(want[0])), (got, want)
+        assert abs(got[1] - want[1]) < (1e-6 if tol > 1e-9 else 1e-12), (got, want)
