@@ -315,7 +315,8 @@ def main():
         "metric": "Pauli expectations/s for M_2 (N=20 qubits) & mana (N=12); fwd vs fwd+grad",
         "value": value, "unit": "Pauli expectations/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "c64 (fp32 transforms, fp64 sums)", "data": "synthetic",
+        "dtype": "f32", "data": "synthetic",
+        "precision": "complex64 state, FP32 transforms, FP64 sums over Pauli strings and shifts",
         "config": {"workload": f"SRE M_2, N={N} qubits, complex64, brick-wall Haar circuit depth {2 * N}, seed {seed}, "
                                + (f"all 4^{N} Pauli strings" if not args.shifts else
                                   f"X-shifts [0, {shifts}) x 2^{N} Z-strings (profiling subset)"),
