@@ -191,6 +191,43 @@ def secondary(hm, S, torch, dev, psi, N):
     return sec
 
 
+def oracle_table(hm, S, torch, dev, target_s: float = 2.0):
+    """GPU (complex64 and complex128, full evaluation, tuned plan) and FP64 oracle (the plain
+    Algorithms 2 and 4 in C with OpenMP, on a prefix of the shifts sized to about target_s) rates at
+    the sizes the method is usually run at.  Rates are per Pauli string / phase-space point."""
+    import oracle
+    rows = []
+    for d, n in ((2, 8), (2, 12), (2, 16), (2, 20), (3, 6), (3, 8), (3, 10), (3, 12)):
+        psi = S.brickwall_haar(n, 2 * n, seed=3000 + n, d=d)
+        v64, w64 = S.to_c64_exact(psi)
+        work = float(d ** n) ** 2
+        rec = {"d": d, "n": n}
+        for name, arr in (("gpu_c64", v64), ("gpu_c128", psi)):
+            x = torch.from_numpy(arr).to(dev)
+            ctx = hm.Context()
+            if d == 2 and n >= 12:
+                hm.autotune(x, 4096, ctx=ctx)
+            fn = (lambda: hm.sre(x, (2.0,), ctx=ctx)) if d == 2 else (lambda: hm.mana(x, ctx=ctx))
+            reps = 1 if work > 1e11 else 20
+            dt, _ = _timed(torch, fn, reps)
+            rec[name] = work / dt
+        shifts = d ** n
+        k = min(shifts, 8)
+        f = (lambda a1: oracle.sre_fwht_sums(w64, (2.0,), 0, a1)) if d == 2 else (lambda a1: oracle.mana_fft_sums(w64, 0, a1))
+        t = time.perf_counter()
+        f(k)
+        dt = time.perf_counter() - t
+        k = max(k, min(shifts, int(k * target_s / max(dt, 1e-4))))
+        t = time.perf_counter()
+        f(k)
+        dt = time.perf_counter() - t
+        rec["oracle"] = k * float(d ** n) / dt
+        rec["oracle_sample"] = f"{k} of {shifts} shifts, {dt:.2f} s"
+        rows.append(rec)
+    return {"unit": "Pauli strings or phase-space points per second", "oracle_threads": oracle.get_threads(),
+            "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -208,6 +245,9 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="skip the plan autotuner (untimed, before warm-up)")
     ap.add_argument("--mana-only", type=int, default=0, metavar="N",
                     help="profiling runs: time only the qutrit mana of an N-qutrit complex64 state per step")
+    ap.add_argument("--oracle-table", action="store_true",
+                    help="print GPU and oracle rates side by side for SRE n = 8, 12, 16, 20 and mana n = 6, 8, 10, 12"
+                         " (oracle on a bounded prefix of the shifts) and exit")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="counter calibration: time a plain device copy of this many MiB five times and exit")
     args = ap.parse_args()
@@ -225,6 +265,9 @@ def main():
     from synth import states as S
 
     dev = torch.device("cuda:0")
+    if args.oracle_table:
+        print(json.dumps(oracle_table(hm, S, torch, dev)), flush=True)
+        return
     if args.mana_only:
         n = args.mana_only
         m = torch.from_numpy(S.to_c64_exact(S.gaussian_state(n, d=3, seed=1212))[0]).to(dev)
