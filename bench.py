@@ -135,7 +135,8 @@ def secondary(hm, S, torch, dev, psi, N):
     """The other rows of the metric, each timed once after a warm-up call (wall clock around the
     call, state resident; plans autotuned where noted): complex128 forward at the headline N
     (tuned), mana at N = 12, fused forward + adjoint against the plain forwards at N = 13
-    (workgroup-resident gradient) and N = 18 (two-pass gradient), the batched form on 1024 states
+    (workgroup-resident gradient) and N = 18 (two-pass gradient), batches of 64 circuit states at
+    N = 12 and 16 (batched fused forward + adjoint, 64 single calls, FP64 forward), the batched form on 1024 states
     of uneven size, and the Monte Carlo estimator at N = 24 (tuned)."""
     import numpy as np
     sec = {}
@@ -169,6 +170,20 @@ def secondary(hm, S, torch, dev, psi, N):
                         ("sre_fwd_c128_n18", lambda: hm.sre(g128, (2.0,)))):
             dt, _ = _timed(torch, fn)
             sec[key] = {"value": 4.0 ** ng / dt, "unit": "Pauli expectations/s", "ms": dt * 1e3}
+        for ng in (12, 16):
+            # a batch of 64 seeded 2-layer RY/RZ + CZ circuit states: batched fused forward + adjoint,
+            # the same states one call at a time, and the plain FP64 forward of the batch
+            angs = np.random.default_rng(4100 + ng).uniform(0, 2 * math.pi, (64, 2, 2, ng))
+            pgs = np.stack([S.ry_rz_cz_state(ng, a) for a in angs])
+            b64 = torch.from_numpy(np.stack([S.to_c64_exact(p)[0] for p in pgs])).to(dev)
+            b128 = [t for t in torch.from_numpy(pgs).to(dev).unbind(0)]
+            for key, fn in (("sre_fwd_grad_c64_n%d_batch64" % ng, lambda: hm.sre_grad_batched(b64, 2.0)),
+                            ("sre_fwd_grad_c64_n%d_64calls" % ng, lambda: [hm.sre_grad(b64[i], 2.0) for i in range(64)]),
+                            ("sre_fwd_c128_n%d_batch64" % ng, lambda: hm.sre_batched(b128, (2.0,)))):
+                dt, _ = _timed(torch, fn, reps=5 if ng <= 12 else 1)
+                sec[key] = {"value": 64 * 4.0 ** ng / dt, "unit": "Pauli expectations/s", "ms": dt * 1e3,
+                            "states": 64}
+            del b64, b128
         rng = np.random.default_rng(5005)
         ns = rng.integers(10, 17, size=1024)
         states = [torch.from_numpy(S.to_c64_exact(S.gaussian_state(int(n), seed=5000 + i))[0]).to(dev)

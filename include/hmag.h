@@ -129,7 +129,8 @@ typedef enum {
   HM_OP_ROW_VALUES = 2, /* hm_sre_row_values (count ignored)                                 */
   HM_OP_SRE_GRAD = 3,   /* hm_sre_grad (count ignored)                                       */
   HM_OP_MANA = 4,       /* hm_mana and hm_mana_partial (count ignored)                       */
-  HM_OP_SRE_SAMPLED = 5 /* hm_sre_sampled; count = n_rows                                    */
+  HM_OP_SRE_SAMPLED = 5, /* hm_sre_sampled; count = n_rows                                   */
+  HM_OP_SRE_GRAD_BATCHED = 6 /* hm_sre_grad_batched; count = batch                          */
 } hm_op;
 hm_status hm_workspace_size(hm_handle h, hm_op op, int n, hm_dtype dtype, int n_q, int64_t count,
                             size_t *bytes);
@@ -180,6 +181,17 @@ hm_status hm_sre_row_values(hm_handle h, const void *psi, int n, hm_dtype dtype,
  * (nothing is stored across shifts); the gradient accumulates in FP64. */
 hm_status hm_sre_grad(hm_handle h, const void *psi, int n, hm_dtype dtype, double q, double *out,
                       void *grad, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* hm_sre_grad for `batch` states of one size n (the same adjoint): psis[s] and grads[s] are host
+ * arrays of device pointers (the arrays are read during the call and not kept); out (device,
+ * 2 * batch doubles) receives {M_q, lost_norm} of state s at out[2 s].  Up to n = 13 (HM_C64) /
+ * 12 (HM_C128) each launch covers up to 64 states, one workgroup row per state; above, the
+ * two-pass kernels take the states one after another on the shared workspace.  Results equal
+ * hm_sre_grad's up to the order of the FP64 partial sums.  Workspace:
+ * hm_workspace_size(HM_OP_SRE_GRAD_BATCHED, count = batch).  batch >= 1. */
+hm_status hm_sre_grad_batched(hm_handle h, const void *const *psis, int n, int batch, hm_dtype dtype,
+                              double q, double *out, void *const *grads, void *ws, size_t ws_bytes,
+                              hipStream_t stream);
 
 /* Many states, each of its own qubit count, in one call (all of one dtype and one q list).
  * psis: HOST array of `batch` DEVICE pointers (one state each); ns: HOST array of their n.

@@ -18,16 +18,16 @@ from typing import Sequence
 
 __all__ = [
     "HmError", "lib", "lib_path", "Context", "default_context", "sre", "sre_partial", "sre_finalize",
-    "sre_rows", "sre_row_values", "sre_grad", "SRE", "sre_batched", "sre_sampled", "autotune", "tuned_plan", "mana", "mana_partial", "workspace_size",
+    "sre_rows", "sre_row_values", "sre_grad", "sre_grad_batched", "SRE", "SREBatched", "sre_batched", "sre_sampled", "autotune", "tuned_plan", "mana", "mana_partial", "workspace_size",
     "HM_C64", "HM_C128", "profile_enable", "profile_reset", "profile_read", "OP_SRE", "OP_SRE_ROWS", "OP_ROW_VALUES", "OP_SRE_GRAD", "OP_MANA",
-    "EXPORTED_SYMBOLS",
+    "OP_SRE_SAMPLED", "OP_SRE_GRAD_BATCHED", "EXPORTED_SYMBOLS",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 lib_path = os.path.join(_HERE, "libhmag.so")
 
 HM_C64, HM_C128 = 0, 1
-OP_SRE, OP_SRE_ROWS, OP_ROW_VALUES, OP_SRE_GRAD, OP_MANA, OP_SRE_SAMPLED = 0, 1, 2, 3, 4, 5
+OP_SRE, OP_SRE_ROWS, OP_ROW_VALUES, OP_SRE_GRAD, OP_MANA, OP_SRE_SAMPLED, OP_SRE_GRAD_BATCHED = 0, 1, 2, 3, 4, 5, 6
 OPT_FORCE_PATH, OPT_BATCH_SHIFTS, OPT_ROW_RB, OPT_COL_RB, OPT_ROW_BITS, OPT_PIPELINE, OPT_LDS_SPLIT, OPT_STREAMS = \
     1, 2, 3, 4, 5, 6, 7, 8
 
@@ -53,6 +53,8 @@ _SIGS = {
     "hm_sre_rows": (_i, [_vp, _vp, _i, _i, _vp, _i64, _dp, _i, _vp, _vp, _sz, _vp]),
     "hm_sre_row_values": (_i, [_vp, _vp, _i, _i, _u64, _vp, _vp, _sz, _vp]),
     "hm_sre_grad": (_i, [_vp, _vp, _i, _i, ctypes.c_double, _vp, _vp, _vp, _sz, _vp]),
+    "hm_sre_grad_batched": (_i, [_vp, ctypes.POINTER(_vp), _i, _i, _i, ctypes.c_double, _vp, ctypes.POINTER(_vp),
+                                 _vp, _sz, _vp]),
     "hm_mana": (_i, [_vp, _vp, _i, _i, _vp, _vp, _sz, _vp]),
     "hm_mana_partial": (_i, [_vp, _vp, _i, _i, _u64, _u64, _vp, _vp, _sz, _vp]),
     "hm_sre_batched_workspace": (_i, [_vp, ctypes.POINTER(_i), _i, _i, _i, ctypes.POINTER(_sz)]),
@@ -390,6 +392,41 @@ def sre_grad(psi, q: float = 2.0, *, ctx: Context | None = None, stream=None):
     return out, grad
 
 
+def sre_grad_batched(states, q: float = 2.0, *, ctx: Context | None = None, stream=None):
+    """hm_sre_grad for several states of one size: states is a GPU tensor of shape (B, 2^n) or a list
+    of B one-dimensional ones.  Returns (float64 tensor (B, 2) of [M_q, lost_norm], gradients in the
+    same form as states: a (B, 2^n) tensor, or a list)."""
+    torch = _torch()
+    ctx = ctx or default_context()
+    as_rows = isinstance(states, torch.Tensor)
+    if as_rows:
+        if states.dim() != 2 or states.shape[0] < 1:
+            raise ValueError("states must have shape (B, 2^n) with B >= 1")
+        states = states.contiguous()
+        sts = list(states.unbind(0))
+    else:
+        sts = list(states)
+    if not sts:
+        raise ValueError("no states")
+    sts = [_state(s, 2) for s in sts]
+    n = sts[0][1]
+    if any(m != n for _, m in sts):
+        raise ValueError("all states must have the same qubit count")
+    sts = [s for s, _ in sts]
+    dt = _dtype_code(sts[0])
+    if any(_dtype_code(s) != dt for s in sts):
+        raise TypeError("all states must share one dtype")
+    B = len(sts)
+    grads = torch.empty((B, 1 << n), dtype=sts[0].dtype, device=sts[0].device)
+    out = torch.empty((B, 2), dtype=torch.float64, device=sts[0].device)
+    ptrs = (_vp * B)(*[s.data_ptr() for s in sts])
+    gptrs = (_vp * B)(*[grads[i].data_ptr() for i in range(B)])
+    ws = _workspace(workspace_size(OP_SRE_GRAD_BATCHED, n, dt, 1, B, ctx), sts[0].device, stream)
+    _check(lib().hm_sre_grad_batched(ctx.h, ptrs, n, B, dt, float(q), _ptr(out), gptrs, _ptr(ws), ws.numel(),
+                                     _stream(stream)))
+    return out, (grads if as_rows else list(grads.unbind(0)))
+
+
 def _make_autograd():
     torch = _torch()
 
@@ -408,19 +445,39 @@ def _make_autograd():
             _, grad = sre_grad(psi, ctx_.q)
             return grad * g.to(grad.real.dtype), None
 
-    return SRE
+    class SREBatched(torch.autograd.Function):
+        """M_q of each row of a (B, 2^n) batch as a differentiable vector; backward runs the batched
+        fused forward + adjoint."""
+
+        @staticmethod
+        def forward(ctx_, psis, q=2.0):
+            ctx_.save_for_backward(psis)
+            ctx_.q = float(q)
+            return sre_batched(list(psis.contiguous().unbind(0)), (float(q),))[:, 0]
+
+        @staticmethod
+        def backward(ctx_, g):
+            (psis,) = ctx_.saved_tensors
+            _, grads = sre_grad_batched(psis, ctx_.q)
+            return grads * g.to(grads.real.dtype)[:, None], None
+
+    return SRE, SREBatched
 
 
-class _LazySRE:
+class _LazyFn:
     _cls = None
 
+    def __init__(self, index: int):
+        self._index = index
+
     def __getattr__(self, item):
-        if _LazySRE._cls is None:
-            _LazySRE._cls = _make_autograd()
-        return getattr(_LazySRE._cls, item)
+        if _LazyFn._cls is None:
+            _LazyFn._cls = _make_autograd()
+        return getattr(_LazyFn._cls[self._index], item)
 
 
-SRE = _LazySRE()
+SRE = _LazyFn(0)
+SREBatched = _LazyFn(1)
 
 
 # ------------------------------------------------------------------------------------------------

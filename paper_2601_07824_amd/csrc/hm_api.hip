@@ -183,6 +183,11 @@ hm_status hm_workspace_size(hm_handle h, hm_op op, int n, hm_dtype dtype, int n_
       if (n < 1 || n > 20) return (hm_status)fail(E_SIZE, "gradient: n = %d outside [1, 20]", n);
       HM_TRY(sre_grad_workspace(plan_opts(h, n, dbl), n, dbl, bytes));
       return HM_OK;
+    case HM_OP_SRE_GRAD_BATCHED:
+      if (n < 1 || n > 20) return (hm_status)fail(E_SIZE, "gradient: n = %d outside [1, 20]", n);
+      if (count < 1 || count > INT32_MAX) return (hm_status)fail(E_ARG, "gradient: count = %lld outside [1, 2^31)", (long long)count);
+      HM_TRY(sre_grad_batched_workspace(plan_opts(h, n, dbl), n, dbl, (int)count, bytes));
+      return HM_OK;
     case HM_OP_SRE_SAMPLED: {
       if (count < 2) return (hm_status)fail(E_ARG, "sampled: count = %lld < 2", (long long)count);
       SrePlan p;
@@ -292,6 +297,27 @@ hm_status hm_sre_grad(hm_handle h, const void *psi, int n, hm_dtype dtype, doubl
   HM_TRY(sre_grad_workspace(o, n, dtype == HM_C128, &need));
   HM_TRY(check_ws(ws, ws_bytes, need));
   return (hm_status)sre_grad_launch(o, n, dtype == HM_C128, psi, q, out, grad, ws, ws_bytes, stream);
+}
+
+hm_status hm_sre_grad_batched(hm_handle h, const void *const *psis, int n, int batch, hm_dtype dtype, double q,
+                              double *out, void *const *grads, void *ws, size_t ws_bytes, hipStream_t stream) {
+  g_err[0] = 0;
+  if (!h) return (hm_status)fail(E_ARG, "h is NULL");
+  HM_TRY(check_dtype(dtype));
+  if (n < 1 || n > 20) return (hm_status)fail(E_SIZE, "gradient: n = %d outside [1, 20]", n);
+  if (batch < 1) return (hm_status)fail(E_ARG, "gradient: batch = %d < 1", batch);
+  if (!psis || !grads) return (hm_status)fail(E_ARG, "psis or grads is NULL");
+  for (int s = 0; s < batch; ++s) {
+    HM_TRY(check_ptr(psis[s], psi_align(dtype), "psis[s]"));
+    HM_TRY(check_ptr(grads[s], psi_align(dtype), "grads[s]"));
+  }
+  HM_TRY(check_ptr(out, 8, "out"));
+  if (!(q > 0.0) || !isfinite(q) || q == 1.0) return (hm_status)fail(E_ARG, "gradient: q = %g must be positive, finite and != 1", q);
+  const PlanOpts o = plan_opts(h, n, dtype == HM_C128);
+  size_t need = 0;
+  HM_TRY(sre_grad_batched_workspace(o, n, dtype == HM_C128, batch, &need));
+  HM_TRY(check_ws(ws, ws_bytes, need));
+  return (hm_status)sre_grad_batched_launch(o, n, dtype == HM_C128, psis, batch, q, out, grads, ws, ws_bytes, stream);
 }
 
 // Workspace of a batched call: the largest need over its size classes.

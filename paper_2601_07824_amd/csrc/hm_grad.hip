@@ -26,13 +26,19 @@
 
 namespace hm {
 
+// One launch covers gridDim.y states of one size; blockIdx.y selects the state, blockIdx.x a
+// strided share of its shifts.
 struct GradArgs {
-  const void *psi;
+  const void *psis[HM_BATCH_PTRS];
   int nf;              // N - 1
   int64_t n_shifts;    // 2^N
   double q;
-  void *gpart;         // [gridDim][2^N] vec2<T>
-  double *spart;       // [gridDim][2]: sum |chi|^2, sum |chi|^{2q}
+  void *gpart;         // [gridDim.y][gridDim.x][2^N] vec2<T>
+  double *spart;       // [gridDim.y][gridDim.x][2]: sum |chi|^2, sum |chi|^{2q}
+};
+
+struct GradOuts {
+  void *g[HM_BATCH_PTRS];
 };
 
 
@@ -60,7 +66,8 @@ __global__ __launch_bounds__((1 << (NL - RB)) < 64 ? 64 : (1 << (NL - RB))) void
   __shared__ vec2<T> gacc[GN];
   __shared__ double red[2 * (NT / 64 + 2)];
 
-  const vec2<T> *__restrict__ psi = (const vec2<T> *)A.psi;
+  const vec2<T> *__restrict__ psi = (const vec2<T> *)A.psis[blockIdx.y];
+  const size_t blk = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
   const uint32_t tau = threadIdx.x;
   const bool tact = tau < (uint32_t)NT;
   const uint32_t tlo = tau & (NT - 1);
@@ -157,23 +164,27 @@ __global__ __launch_bounds__((1 << (NL - RB)) < 64 ? 64 : (1 << (NL - RB))) void
     }
     __syncthreads();
   }
-  vec2<T> *gp = (vec2<T> *)A.gpart + (size_t)blockIdx.x * GN;
+  vec2<T> *gp = (vec2<T> *)A.gpart + blk * GN;
   for (uint32_t i = tau; i < (uint32_t)GN; i += blockDim.x) gp[i] = gacc[i];
   // block sums of s1, sq (fixed order)
   constexpr int BT = NT < 64 ? 64 : NT;
   const double t1 = seg_sum<BT, BT>(s1, red, tau);
   const double tq = seg_sum<BT, BT>(sq, red + (BT / 64 + 1), tau);
   if (tau == 0) {
-    A.spart[2 * blockIdx.x] = t1;
-    A.spart[2 * blockIdx.x + 1] = tq;
+    A.spart[2 * blk] = t1;
+    A.spart[2 * blk + 1] = tq;
   }
 }
 
-// totals over blocks -> out = {M_q, lost_norm}; scale = 2 / ((1 - q) S_q ln 2) for the gradient
+// totals over blocks -> out = {M_q, lost_norm}; scale = 2 / ((1 - q) S_q ln 2) for the gradient.
+// Workgroup s handles state s: spart[s][nblk][2] -> out[2 s .. 2 s + 1], scale[s].
 __global__ __launch_bounds__(256) void k_grad_totals(const double *spart, int nblk, int N, double q, double *out,
                                                     double *scale) {
   __shared__ double r1[256], rq[256];
   const uint32_t t = threadIdx.x;
+  spart += (size_t)blockIdx.x * 2 * nblk;
+  out += 2 * blockIdx.x;
+  scale += blockIdx.x;
   double a = 0.0, b = 0.0;
   for (int i = t; i < nblk; i += 256) {
     a += spart[2 * i];
@@ -197,10 +208,14 @@ __global__ __launch_bounds__(256) void k_grad_totals(const double *spart, int nb
   }
 }
 
+// grad_s[y] = scale[s] * sum over blocks of G partials (fixed order); blockIdx.y = state s.
 template <typename T>
-__global__ void k_grad_reduce(const vec2<T> *gpart, int nblk, int64_t n, const double *scale, vec2<T> *grad) {
+__global__ void k_grad_reduce(const vec2<T> *gpart, int nblk, int64_t n, const double *scale, GradOuts outs) {
   const int64_t y = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (y >= n) return;
+  vec2<T> *grad = (vec2<T> *)outs.g[blockIdx.y];
+  gpart += (size_t)blockIdx.y * nblk * n;
+  scale += blockIdx.y;
   double gr = 0.0, gi = 0.0;
   for (int b = 0; b < nblk; ++b) {
     const vec2<T> v = gpart[(size_t)b * n + y];
@@ -219,14 +234,21 @@ static constexpr int GRAD_MAX_BLOCKS = 256;
 
 static int grad_max_n(int dbl) { return dbl ? 12 : 13; }
 
-static int grad_blocks(int N) {
+// Workgroups per state: 256 for one to four states, then fewer so that a launch holds about 1024
+// workgroups (each sums its own G partial, so fewer per state keeps the final reduction short).
+static int grad_blocks(int N, int states) {
+  int nb = GRAD_MAX_BLOCKS;
+  while (nb > 4 && (int64_t)nb * states > 1024) nb >>= 1;
   const int64_t s = (int64_t)1 << N;
-  return (int)(s < GRAD_MAX_BLOCKS ? s : GRAD_MAX_BLOCKS);
+  return (int)(s < nb ? s : nb);
 }
 
-static size_t grad1_workspace(int N, int dbl) {
-  const size_t nb = (size_t)grad_blocks(N);
-  return align256(nb * ((size_t)1 << N) * (dbl ? 16 : 8)) + align256(nb * 2 * sizeof(double)) + 256;
+static int grad_chunk(int batch) { return batch < HM_BATCH_PTRS ? batch : HM_BATCH_PTRS; }
+
+static size_t grad1_workspace(int N, int dbl, int states) {
+  const size_t nb = (size_t)grad_blocks(N, states) * states;
+  return align256(nb * ((size_t)1 << N) * (dbl ? 16 : 8)) + align256(nb * 2 * sizeof(double)) +
+         align256((size_t)states * sizeof(double));
 }
 
 // Two-pass plan of the gradient: default split and tiles, sequential launches.
@@ -239,20 +261,32 @@ static int grad2_plan(const PlanOpts &o, int N, int dbl, SrePlan *p) {
   int e = sre_plan(N, dbl, g, p);
   if (e) return e;
   if (p->nf < 11 || p->nf > 19) return fail(E_UNSUPPORTED, "gradient: two-pass kernels cover n in [12, 20] (n = %d)", N);
-  // Batches of at most 2^nl aligned shifts: every batch after the first then shares its top bit and
-  // its bits above nl, which the fused backward-row + accumulation kernel needs.
-  if (!o.batch && p->batch > (1 << p->nl)) {
+  if (o.batch) return OK;
+  if (N <= 16) {
+    // Up to n = 16 a batch of 2^nl shifts is a small launch (2^nl <= 256): take 256 MiB (FP32) /
+    // 128 MiB (FP64) exchange batches through the separate backward-row and accumulation kernels.
+    const int64_t want = ((int64_t)(dbl ? 128 : 256) << 20) / (((int64_t)1 << p->nf) * (dbl ? 16 : 8));
+    const int64_t all = (int64_t)1 << N;
+    g.batch = want < all ? want : all;
+  } else {
+    // Batches of at most 2^nl aligned shifts: every batch after the first then shares its top bit
+    // and its bits above nl, which the fused backward-row + accumulation kernel needs.
+    if (p->batch <= (1 << p->nl)) return OK;
     g.batch = (int64_t)1 << p->nl;
-    if ((e = sre_plan(N, dbl, g, p))) return e;
   }
-  return OK;
+  return sre_plan(N, dbl, g, p);
 }
 
 static bool grad_two_pass(const PlanOpts &o, int N, int dbl) { return N > grad_max_n(dbl) || (o.force_path == 2 && N >= 12); }
 
-int sre_grad_workspace(const PlanOpts &o, int N, int dbl, size_t *bytes) {
+int sre_grad_batched_workspace(const PlanOpts &o, int N, int dbl, int batch, size_t *bytes) {
+  if (batch < 1) return fail(E_ARG, "gradient: batch = %d < 1", batch);
   if (!grad_two_pass(o, N, dbl)) {
-    *bytes = grad1_workspace(N, dbl);
+    // full chunks of HM_BATCH_PTRS states and a shorter last one, which may take more workgroups
+    const size_t full = grad1_workspace(N, dbl, grad_chunk(batch));
+    const int rest = batch % HM_BATCH_PTRS;
+    const size_t last = rest ? grad1_workspace(N, dbl, rest) : 0;
+    *bytes = full > last ? full : last;
     return OK;
   }
   SrePlan p;
@@ -262,6 +296,10 @@ int sre_grad_workspace(const PlanOpts &o, int N, int dbl, size_t *bytes) {
   return OK;
 }
 
+int sre_grad_workspace(const PlanOpts &o, int N, int dbl, size_t *bytes) {
+  return sre_grad_batched_workspace(o, N, dbl, 1, bytes);
+}
+
 int grad_totals_launch(const double *shift_sums, int64_t n_shifts, int N, double q, double *out, double *scale,
                        hipStream_t st) {
   hipLaunchKernelGGL(k_grad_totals, dim3(1), dim3(256), 0, st, shift_sums, (int)n_shifts, N, q, out, scale);
@@ -269,37 +307,45 @@ int grad_totals_launch(const double *shift_sums, int64_t n_shifts, int N, double
 }
 
 template <typename T, int RB, int NL>
-static void launch_grad_nl(const GradArgs &A, int nblk, hipStream_t st) {
+static void launch_grad_nl(const GradArgs &A, int nblk, int states, hipStream_t st) {
   constexpr int NT = (1 << (NL - RB)) < 64 ? 64 : (1 << (NL - RB));
   ProfScope prof("sre_grad_resident", st);
-  if (A.q == 2.0) hipLaunchKernelGGL((k_sre_grad_resident<T, RB, NL, true>), dim3(nblk), dim3(NT), 0, st, A);
-  else hipLaunchKernelGGL((k_sre_grad_resident<T, RB, NL, false>), dim3(nblk), dim3(NT), 0, st, A);
+  const dim3 grid(nblk, states);
+  if (A.q == 2.0) hipLaunchKernelGGL((k_sre_grad_resident<T, RB, NL, true>), grid, dim3(NT), 0, st, A);
+  else hipLaunchKernelGGL((k_sre_grad_resident<T, RB, NL, false>), grid, dim3(NT), 0, st, A);
 }
 
+// Up to HM_BATCH_PTRS states of size N: psis[s] -> out[2 s .. 2 s + 1], grads[s].
 template <typename T>
-static int grad_t(int N, const void *psi, double q, double *out, void *grad, void *ws, hipStream_t st) {
-  const int nblk = grad_blocks(N);
+static int grad_t(int N, const void *const *psis, int states, double q, double *out, void *const *grads, void *ws,
+                  hipStream_t st) {
+  const int nblk = grad_blocks(N, states);
+  const size_t nb = (size_t)nblk * states;
   char *w = (char *)ws;
   GradArgs A{};
-  A.psi = psi;
+  GradOuts G{};
+  for (int s = 0; s < states; ++s) {
+    A.psis[s] = psis[s];
+    G.g[s] = grads[s];
+  }
   A.nf = N - 1;
   A.n_shifts = (int64_t)1 << N;
   A.q = q;
   A.gpart = w;
-  A.spart = (double *)(w + align256((size_t)nblk * ((size_t)1 << N) * sizeof(vec2<T>)));
-  double *scale = A.spart + align256((size_t)nblk * 2 * sizeof(double)) / sizeof(double);
+  A.spart = (double *)(w + align256(nb * ((size_t)1 << N) * sizeof(vec2<T>)));
+  double *scale = A.spart + align256(nb * 2 * sizeof(double)) / sizeof(double);
   const int NL = N - 1;
   constexpr int RBmax = sizeof(T) == 4 ? 4 : 3;  // R = 16 (FP32) or 8 (FP64) values per thread: no spills
 #define HM_G(nl, rb) \
   case nl:           \
-    launch_grad_nl<T, rb, nl>(A, nblk, st); \
+    launch_grad_nl<T, rb, nl>(A, nblk, states, st); \
     break;
   switch (NL) {
     HM_G(0, 0) HM_G(1, 1) HM_G(2, 2) HM_G(3, 3) HM_G(4, RBmax) HM_G(5, RBmax) HM_G(6, RBmax) HM_G(7, RBmax)
-    HM_G(8, RBmax) HM_G(9, RBmax) HM_G(10, RBmax) HM_G(11, RBmax)
+    HM_G(8, RBmax) HM_G(9, RBmax) HM_G(10, 3) HM_G(11, 3)
     case 12:
       if constexpr (sizeof(T) == 4) {
-        launch_grad_nl<T, 4, 12>(A, nblk, st);
+        launch_grad_nl<T, 3, 12>(A, nblk, states, st);
         break;
       }
       [[fallthrough]];
@@ -307,25 +353,43 @@ static int grad_t(int N, const void *psi, double q, double *out, void *grad, voi
       return fail(E_SIZE, "gradient: n = %d above the workgroup-resident limit %d", N, grad_max_n(sizeof(T) == 8));
   }
 #undef HM_G
-  hipLaunchKernelGGL(k_grad_totals, dim3(1), dim3(256), 0, st, A.spart, nblk, N, q, out, scale);
+  hipLaunchKernelGGL(k_grad_totals, dim3(states), dim3(256), 0, st, A.spart, nblk, N, q, out, scale);
   const int64_t n = (int64_t)1 << N;
-  hipLaunchKernelGGL(k_grad_reduce<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (const vec2<T> *)A.gpart,
-                     nblk, n, (const double *)scale, (vec2<T> *)grad);
+  hipLaunchKernelGGL(k_grad_reduce<T>, dim3((unsigned)((n + 255) / 256), states), dim3(256), 0, st,
+                     (const vec2<T> *)A.gpart, nblk, n, (const double *)scale, G);
   return hipPeekAtLastError() == hipSuccess ? OK : fail(E_HIP, "gradient launch: %s", hipGetErrorString(hipGetLastError()));
+}
+
+int sre_grad_batched_launch(const PlanOpts &o, int N, int dbl, const void *const *psis, int batch, double q,
+                            double *out, void *const *grads, void *ws, size_t ws_bytes, hipStream_t st) {
+  size_t need = 0;
+  int e = sre_grad_batched_workspace(o, N, dbl, batch, &need);
+  if (e) return e;
+  if (ws_bytes < need) return fail(E_WORKSPACE, "gradient workspace of %zu bytes, %zu needed", ws_bytes, need);
+  if (grad_two_pass(o, N, dbl)) {
+    // one state after another on the same workspace (stream order separates them)
+    SrePlan p;
+    if ((e = grad2_plan(o, N, dbl, &p))) return e;
+    for (int s = 0; s < batch; ++s) {
+      e = dbl ? sre_grad2_f64(p, psis[s], q, out + 2 * s, grads[s], ws, st)
+              : sre_grad2_f32(p, psis[s], q, out + 2 * s, grads[s], ws, st);
+      if (e) return e;
+    }
+    return OK;
+  }
+  // resident: chunks of up to HM_BATCH_PTRS states, one launch each, sharing the workspace in order
+  for (int s0 = 0; s0 < batch; s0 += HM_BATCH_PTRS) {
+    const int cnt = grad_chunk(batch - s0);
+    e = dbl ? grad_t<double>(N, psis + s0, cnt, q, out + 2 * s0, grads + s0, ws, st)
+            : grad_t<float>(N, psis + s0, cnt, q, out + 2 * s0, grads + s0, ws, st);
+    if (e) return e;
+  }
+  return OK;
 }
 
 int sre_grad_launch(const PlanOpts &o, int N, int dbl, const void *psi, double q, double *out, void *grad, void *ws,
                     size_t ws_bytes, hipStream_t st) {
-  size_t need = 0;
-  int e = sre_grad_workspace(o, N, dbl, &need);
-  if (e) return e;
-  if (ws_bytes < need) return fail(E_WORKSPACE, "gradient workspace of %zu bytes, %zu needed", ws_bytes, need);
-  if (grad_two_pass(o, N, dbl)) {
-    SrePlan p;
-    if ((e = grad2_plan(o, N, dbl, &p))) return e;
-    return dbl ? sre_grad2_f64(p, psi, q, out, grad, ws, st) : sre_grad2_f32(p, psi, q, out, grad, ws, st);
-  }
-  return dbl ? grad_t<double>(N, psi, q, out, grad, ws, st) : grad_t<float>(N, psi, q, out, grad, ws, st);
+  return sre_grad_batched_launch(o, N, dbl, &psi, 1, q, out, &grad, ws, ws_bytes, st);
 }
 
 }  // namespace hm

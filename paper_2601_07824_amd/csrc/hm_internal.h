@@ -167,6 +167,11 @@ size_t sre_row_values_workspace(int N, int dbl);
 int sre_grad_launch(const PlanOpts &opts, int N, int dbl, const void *psi, double q, double *out, void *grad,
                     void *ws, size_t ws_bytes, hipStream_t stream);
 int sre_grad_workspace(const PlanOpts &opts, int N, int dbl, size_t *bytes);
+// batch states of one size: psis[s] -> out[2 s .. 2 s + 1], grads[s]; one resident launch per
+// HM_BATCH_PTRS states, or the two-pass kernels state after state on one workspace.
+int sre_grad_batched_launch(const PlanOpts &opts, int N, int dbl, const void *const *psis, int batch, double q,
+                            double *out, void *const *grads, void *ws, size_t ws_bytes, hipStream_t stream);
+int sre_grad_batched_workspace(const PlanOpts &opts, int N, int dbl, int batch, size_t *bytes);
 int grad_totals_launch(const double *shift_sums, int64_t n_shifts, int N, double q, double *out, double *scale,
                        hipStream_t stream);
 int sre_grad2_f32(const SrePlan &p, const void *psi, double q, double *out, void *grad, void *ws, hipStream_t st);

@@ -232,3 +232,32 @@ def test_gradient_workspace_all_sizes(L, h):
             assert L.hm_workspace_size(hh, 3, 12, dt, 1, 0, ctypes.byref(b)) == HM_OK
     finally:
         L.hm_destroy(hh)
+
+
+def test_batched_gradient_workspace_and_errors(L, h):
+    b = ctypes.c_size_t()
+    one = ctypes.c_size_t()
+    for dt in (0, 1):
+        for n in range(1, 21):
+            assert L.hm_workspace_size(h, 3, n, dt, 1, 0, ctypes.byref(one)) == HM_OK
+            for B in (1, 5, 64, 65, 130):
+                assert L.hm_workspace_size(h, 6, n, dt, 1, B, ctypes.byref(b)) == HM_OK, (n, dt, B, L.hm_last_error())
+                assert b.value >= 256
+                if B == 1:
+                    assert b.value == one.value  # a batch of one is the single-state call
+        assert L.hm_workspace_size(h, 6, 21, dt, 1, 4, ctypes.byref(b)) == HM_E_SIZE
+        assert L.hm_workspace_size(h, 6, 12, dt, 1, 0, ctypes.byref(b)) == HM_E_ARG
+    good = P(0x100000)
+    ptrs = (P * 2)(good, good)
+    ws = P(0x200000)
+    out = P(0x300000)
+    assert L.hm_sre_grad_batched(None, ptrs, 8, 2, 0, 2.0, out, ptrs, ws, 1 << 30, None) == HM_E_ARG
+    assert L.hm_sre_grad_batched(h, ptrs, 8, 0, 0, 2.0, out, ptrs, ws, 1 << 30, None) == HM_E_ARG
+    assert L.hm_sre_grad_batched(h, None, 8, 2, 0, 2.0, out, ptrs, ws, 1 << 30, None) == HM_E_ARG
+    assert L.hm_sre_grad_batched(h, ptrs, 8, 2, 0, 2.0, out, None, ws, 1 << 30, None) == HM_E_ARG
+    assert L.hm_sre_grad_batched(h, ptrs, 8, 2, 0, 1.0, out, ptrs, ws, 1 << 30, None) == HM_E_ARG
+    assert L.hm_sre_grad_batched(h, ptrs, 21, 2, 0, 2.0, out, ptrs, ws, 1 << 30, None) == HM_E_SIZE
+    assert L.hm_sre_grad_batched(h, ptrs, 8, 2, 7, 2.0, out, ptrs, ws, 1 << 30, None) == HM_E_DTYPE
+    assert L.hm_sre_grad_batched(h, ptrs, 8, 2, 0, 2.0, out, ptrs, ws, 16, None) == HM_E_WORKSPACE
+    bad = (P * 2)(good, P(0x100004))  # misaligned second state
+    assert L.hm_sre_grad_batched(h, bad, 8, 2, 0, 2.0, out, ptrs, ws, 1 << 30, None) == HM_E_ALIGN
