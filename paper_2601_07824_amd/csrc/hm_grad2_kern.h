@@ -108,7 +108,9 @@ struct FusedArgs {
   int groups;
 };
 
-template <typename T, int NT, int RB, int NL, bool SPLIT>
+// RBW: register tile of the row pass that wrote the exchange (its column permutation: row position
+// P sits at column (P mod 2^RBW) 2^(NL-RBW) + P / 2^RBW).  RB <= RBW is this kernel's own tile.
+template <typename T, int NT, int RB, int RBW, int NL, bool SPLIT>
 __global__ __launch_bounds__(NT) void k_grad_rowback_accum(FusedArgs F) {
   using Sh = RowShape<T, NT, RB, NL, SPLIT>;
   constexpr int R = 1 << RB;
@@ -149,12 +151,16 @@ __global__ __launch_bounds__(NT) void k_grad_rowback_accum(FusedArgs F) {
   for (int64_t sb = s_lo; sb < s_hi; sb += G) {
     const int64_t s = sb + g;
     const bool active = s < s_hi;
-    const uint32_t ob = ((((uint32_t)s << F.nh) + ch) << NL) | tlo;
+    static_assert(RB <= RBW && RBW <= NL, "reader tile within the writer's");
+    const uint32_t ob = (((uint32_t)s << F.nh) + ch) << NL;
     T re[R], im[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
+      // layout S = 0 of this kernel: register r of thread tlo holds row position r + R tlo
+      const uint32_t P = (uint32_t)r + (tlo << RB);
+      const uint32_t col = ((P & ((1u << RBW) - 1u)) << (NL - RBW)) | (P >> RBW);
       vec2<T> v{T(0), T(0)};
-      if (active) v = ld32(ex, ob + ((uint32_t)r << S0));
+      if (active) v = ld32(ex, ob + col);
       re[r] = v.x;
       im[r] = v.y;
     }
@@ -328,6 +334,14 @@ __global__ void k_zero2(double2 *p, int64_t n) {
   if (i < n) p[i] = double2{0.0, 0.0};
 }
 
+// Register tile of the fused backward-row + accumulation kernel: 2^3 values per thread for rows of
+// 2^8 and 2^9 (half the registers of 2^4, so twice the waves; measured faster there), 2^4 otherwise
+// (rows of 2^10 would need a fourth round).
+constexpr int fused_rb(int nl) { return nl == 8 || nl == 9 ? 3 : 4; }
+// Register tile of the gradient's forward row pass (the plan's row_rb), which fixes the exchange's
+// column permutation.
+constexpr int GRAD_ROW_RB = 4;
+
 // ---- launchers (default two-pass split only) -----------------------------------------------------
 template <typename T, int RB, int NF, bool SPLIT>
 static void grad2_launch_nf(int step, RowPassArgs &A, ColPassArgs &C, const FusedArgs *F, bool q2, hipStream_t st) {
@@ -356,13 +370,14 @@ static void grad2_launch_nf(int step, RowPassArgs &A, ColPassArgs &C, const Fuse
     ProfScope prof("sre_grad_rowback", st);
     hipLaunchKernelGGL((k_sre_rowback<T, NTR, RBR, NL, SPLIT>), grid, block, 0, st, A);
   } else {
-    // fused backward rows + accumulation: 128 threads x 2^4 values, 2^(11 - NL) shifts in flight
-    constexpr int RBR = 4;
+    // fused backward rows + accumulation: 128 threads x 2^RBR values, 2^(7 + RBR - NL) shifts in
+    // flight
+    constexpr int RBR = fused_rb(NL);
     constexpr int NTF = 128;
     static_assert(ilog2c(NTF) + RBR >= NL, "fused tile must hold a whole row");
     const dim3 grid((unsigned)(((int64_t)1 << F->nh) * F->groups)), block(NTF);
     ProfScope prof("sre_grad_rowback_accum", st);
-    hipLaunchKernelGGL((k_grad_rowback_accum<T, NTF, RBR, NL, SPLIT>), grid, block, 0, st, *F);
+    hipLaunchKernelGGL((k_grad_rowback_accum<T, NTF, RBR, GRAD_ROW_RB, NL, SPLIT>), grid, block, 0, st, *F);
   }
 }
 
@@ -458,6 +473,7 @@ int grad2_t(const SrePlan &p, const void *psi, double q, double *out, void *grad
     const int j0 = a_first ? 63 - __builtin_clzll(a_first) : -1;
     const int j1 = 63 - __builtin_clzll(a_last | 1);
     const bool fuse = a_first != 0 && j0 == j1 && (j0 < p.nl || (a_first >> p.nl) == (a_last >> p.nl));
+    if (fuse && p.row_rb != GRAD_ROW_RB) return fail(E_UNSUPPORTED, "fused gradient kernel: row tile %d", p.row_rb);
     if (fuse) {
       FusedArgs F{};
       F.psi = psi;
@@ -470,8 +486,8 @@ int grad2_t(const SrePlan &p, const void *psi, double q, double *out, void *grad
       F.j = j0;
       F.ah = (uint32_t)(a_first >> p.nl);
       F.gpart = gpart;
-      // shift groups: at least one round of the 2^(11 - nl) shifts a workgroup holds at a time
-      const int64_t gf = nb >> (11 - p.nl);
+      // shift groups: at least one round of the 2^(7 + rb - nl) shifts a workgroup holds at a time
+      const int64_t gf = nb >> (7 + fused_rb(p.nl) - p.nl);
       F.groups = (int)(gf < 1 ? 1 : gf < groups ? gf : groups);
       e = p.split ? grad2_launch<T, true>(nf, 4, A, C, &F, q2, st) : grad2_launch<T, false>(nf, 4, A, C, &F, q2, st);
       if (e) return e;

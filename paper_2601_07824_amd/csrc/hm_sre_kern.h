@@ -334,7 +334,10 @@ __device__ __forceinline__ void colpass_tiles(const ColPassArgs &A, int64_t t0, 
       }
       wht_regs<T, R, cp_L(NH, RB, CB, 0), cp_H(NH, RB, CB, 0)>(re, im);
       vec2<T> *exw = (vec2<T> *)A.exch;
-      const uint32_t base = ((uint32_t)slot << (NH + A.nl)) + ((uint32_t)cb << CB) + col;
+      uint32_t base = ((uint32_t)slot << (NH + A.nl)) + ((uint32_t)cb << CB) + col;
+      // recompute the write addresses instead of keeping the loads' 64-bit addresses live across
+      // the transforms (an empty asm hides that base equals the load base)
+      asm volatile("" : "+v"(base));
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const uint32_t row = (uint32_t)r | (rowhi << RB);

@@ -52,3 +52,25 @@ def test_fused_gradient_rows_own_disjoint_entries(n):
                         assert owner.setdefault(t, ch) == ch
         assert len(owner) == 1 << n  # every entry has exactly one owning row
     assert checked > 0
+
+
+@pytest.mark.parametrize("nl", [6, 8, 9, 10])
+@pytest.mark.parametrize("rb", [3, 4])
+def test_fused_gradient_reads_the_row_pass_column_permutation(nl, rb):
+    """The row pass (2^4-value register tiles) stores register r4 of thread t4, row position
+    r4 + 16 t4, at column r4 2^(nl-4) + t4.  The fused kernel with 2^rb-value tiles wants register r
+    of thread t at position r + 2^rb t and reads column (P mod 16) 2^(nl-4) + P / 16 for it: every
+    column is read once and holds the position the kernel expects."""
+    rbw = 4
+    at = {}
+    for t4 in range(1 << (nl - rbw)):
+        for r4 in range(1 << rbw):
+            at[(r4 << (nl - rbw)) | t4] = r4 + (t4 << rbw)
+    seen = set()
+    for t in range(1 << (nl - rb)):
+        for r in range(1 << rb):
+            p = r + (t << rb)
+            col = ((p & ((1 << rbw) - 1)) << (nl - rbw)) | (p >> rbw)
+            assert at[col] == p
+            seen.add(col)
+    assert seen == set(range(1 << nl))
