@@ -86,7 +86,9 @@ const char *hm_version(void);
  *   HM_OPT_STREAMS: sequential two-pass launches on 1 stream (the caller's) or 2 (batches alternate
  *     between the caller's stream and an internal stream of the library, forked from and joined
  *     back into the caller's stream with events, so results stay stream-ordered; twice the
- *     exchange workspace).
+ *     exchange workspace).  Applies to SRE and mana (default 1 for both).  The FP64 partial
+ *     sums of two-stream mana are grouped per stream, so its last bits differ from the
+ *     one-stream result (each is deterministic).
  * A combination outside the built kernels makes the SRE calls return HM_E_UNSUPPORTED. */
 typedef enum {
   HM_OPT_FORCE_PATH = 1,

@@ -199,7 +199,7 @@ hm_status hm_workspace_size(hm_handle h, hm_op op, int n, hm_dtype dtype, int n_
       if (n < 1 || n > 16) return (hm_status)fail(E_SIZE, "mana: n = %d outside [1, 16]", n);
       uint64_t D = 1;
       for (int i = 0; i < n; ++i) D *= 3;
-      *bytes = mana_workspace(n, dbl, h->opts.batch, D);
+      *bytes = mana_workspace(n, dbl, h->opts.batch, (int)h->opts.streams, D);
       return HM_OK;
     }
   }
@@ -469,8 +469,8 @@ hm_status hm_mana(hm_handle h, const void *psi, int n, hm_dtype dtype, double *o
   HM_TRY(check_ptr(out, 8, "out"));
   uint64_t D = 1;
   for (int i = 0; i < n; ++i) D *= 3;
-  HM_TRY(check_ws(ws, ws_bytes, mana_workspace(n, dtype == HM_C128, h->opts.batch, D)));
-  return (hm_status)mana_launch(n, dtype == HM_C128, h->opts.batch, psi, 0, D, nullptr, out, ws, ws_bytes, stream);
+  HM_TRY(check_ws(ws, ws_bytes, mana_workspace(n, dtype == HM_C128, h->opts.batch, (int)h->opts.streams, D)));
+  return (hm_status)mana_launch(n, dtype == HM_C128, h->opts.batch, (int)h->opts.streams, psi, 0, D, nullptr, out, ws, ws_bytes, stream);
 }
 
 hm_status hm_mana_partial(hm_handle h, const void *psi, int n, hm_dtype dtype, uint64_t a0, uint64_t a1, double *sums,
@@ -484,9 +484,9 @@ hm_status hm_mana_partial(hm_handle h, const void *psi, int n, hm_dtype dtype, u
   uint64_t D = 1;
   for (int i = 0; i < n; ++i) D *= 3;
   if (a0 > a1 || a1 > D) return (hm_status)fail(E_ARG, "shift range [%llu, %llu) not inside [0, 3^%d]", (unsigned long long)a0, (unsigned long long)a1, n);
-  HM_TRY(check_ws(ws, ws_bytes, mana_workspace(n, dtype == HM_C128, h->opts.batch, a1 - a0)));
+  HM_TRY(check_ws(ws, ws_bytes, mana_workspace(n, dtype == HM_C128, h->opts.batch, (int)h->opts.streams, a1 - a0)));
   if (a1 == a0) return (hm_status)fill_dev(sums, 3, 0.0, stream);
-  return (hm_status)mana_launch(n, dtype == HM_C128, h->opts.batch, psi, a0, a1, sums, nullptr, ws, ws_bytes, stream);
+  return (hm_status)mana_launch(n, dtype == HM_C128, h->opts.batch, (int)h->opts.streams, psi, a0, a1, sums, nullptr, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

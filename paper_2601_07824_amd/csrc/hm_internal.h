@@ -181,9 +181,9 @@ size_t sre_grad2_workspace_f64(const SrePlan &p);
 
 // ---- Mana ------------------------------------------------------------------------------------
 // batch: X-shifts per two-pass launch pair (0 = automatic; HM_OPT_BATCH_SHIFTS of the handle).
-int mana_launch(int N, int dbl, int64_t batch, const void *psi, uint64_t a0, uint64_t a1, double *sums, double *out,
-                void *ws,
-                size_t ws_bytes, hipStream_t stream);
-size_t mana_workspace(int N, int dbl, int64_t batch, uint64_t n_shifts);
+// streams: two-pass batches alternate over 1 or 2 streams (0 = automatic, HM_OPT_STREAMS).
+int mana_launch(int N, int dbl, int64_t batch, int streams, const void *psi, uint64_t a0, uint64_t a1, double *sums,
+                double *out, void *ws, size_t ws_bytes, hipStream_t stream);
+size_t mana_workspace(int N, int dbl, int64_t batch, int streams, uint64_t n_shifts);
 
 }  // namespace hm

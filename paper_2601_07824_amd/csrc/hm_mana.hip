@@ -435,13 +435,22 @@ static constexpr int MANA_GRID = 2048;  // fixed grid: per-block accumulators li
 
 struct ManaPlan {
   int N, dbl, path, nl, nh, RT, batch_pairs;
+  int lanes;  // two-pass batches alternate over this many streams (own exchange and accumulators)
 };
 
-// batch: X-shifts per two-pass launch pair (0 = 128 MiB of exchange).
-static int mana_plan(int N, int dbl, int64_t batch, ManaPlan *p) {
+// Two-pass default: one lane.  Two lanes let the VALU-bound row pass of one batch overlap the
+// memory-bound column pass of the other, but measured no faster at n = 12 (645 ms with 44-shift
+// batches against 641 ms on one stream; 713 ms with two 192 MiB exchanges, which no longer fit the
+// memory-side cache together).
+static constexpr int MANA_STREAMS_DEFAULT = 1;
+
+// batch: X-shifts per two-pass launch pair (0 = 192 MiB of exchange); streams: 0 (default), 1, 2.
+static int mana_plan(int N, int dbl, int64_t batch, int streams, ManaPlan *p) {
+  if (streams < 0 || streams > 2) return fail(E_ARG, "mana: streams = %d outside [0, 2]", streams);
   ManaPlan P{};
   P.N = N;
   P.dbl = dbl;
+  P.lanes = 1;
   P.RT = dbl ? 2 : 3;
   if (N < P.RT) P.RT = N;  // tiny states: one thread holds a whole vector
   const int onepass_max = dbl ? 7 : 8;  // one row of 3^N values per <= 243 threads
@@ -464,17 +473,21 @@ static int mana_plan(int N, int dbl, int64_t batch, ManaPlan *p) {
     if ((size_t)b * per_pair > (3ull << 30)) b = (int64_t)((3ull << 30) / per_pair);  // 32-bit offsets
     if (b < 1) b = 1;
     P.batch_pairs = (int)b;
+    P.lanes = streams ? streams : MANA_STREAMS_DEFAULT;
   }
   *p = P;
   return OK;
 }
 
-size_t mana_workspace(int N, int dbl, int64_t batch, uint64_t n_shifts) {
+static size_t mana_acc_bytes(const ManaPlan &P) { return align256((size_t)MANA_GRID * 3 * sizeof(double)); }
+
+// [row accumulators][column accumulators x lanes][exchange x lanes]
+size_t mana_workspace(int N, int dbl, int64_t batch, int streams, uint64_t n_shifts) {
   (void)n_shifts;
   ManaPlan P;
-  if (N < 1 || N > 16 || mana_plan(N, dbl, batch, &P) != OK) return 256;
-  size_t b = align256((size_t)MANA_GRID * 3 * sizeof(double)) * 2;  // row / column accumulators
-  if (P.path == 2) b += align256((size_t)P.batch_pairs * (size_t)pow3c(N) * (dbl ? 16 : 8));
+  if (N < 1 || N > 16 || mana_plan(N, dbl, batch, streams, &P) != OK) return 256;
+  size_t b = mana_acc_bytes(P) * (1 + P.lanes);
+  if (P.path == 2) b += (size_t)P.lanes * align256((size_t)P.batch_pairs * (size_t)pow3c(N) * (dbl ? 16 : 8));
   return b;
 }
 
@@ -535,11 +548,11 @@ template <typename T>
 static int mana_t(const ManaPlan &P, const void *psi, uint64_t a0, uint64_t a1, double *sums, double *out, void *ws,
                   hipStream_t st) {
   char *w = (char *)ws;
+  const size_t accb = mana_acc_bytes(P);
   double *acc_row = (double *)w;
-  double *acc_col = (double *)(w + align256((size_t)MANA_GRID * 3 * sizeof(double)));
-  void *exch = w + 2 * align256((size_t)MANA_GRID * 3 * sizeof(double));
+  double *acc_col = (double *)(w + accb);  // lane l: acc_col + l * MANA_GRID * 3 (contiguous)
   {
-    const int64_t nz = (int64_t)(2 * align256((size_t)MANA_GRID * 3 * sizeof(double)) / sizeof(double));
+    const int64_t nz = (int64_t)(accb * (1 + P.lanes) / sizeof(double));
     hipLaunchKernelGGL(k_mana_zero, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, st, acc_row, nz);
   }
   const int64_t n_pairs = (int64_t)((a1 - a0 + 1) / 2);
@@ -564,42 +577,72 @@ static int mana_t(const ManaPlan &P, const void *psi, uint64_t a0, uint64_t a1, 
     }
     if (e) return e;
     hipLaunchKernelGGL(k_mana_total, dim3(1), dim3(256), 0, st, acc_row, (int64_t)MANA_GRID, P.N, sums, out);
-  } else {
-    for (int64_t p0 = 0; p0 < n_pairs; p0 += P.batch_pairs) {
-      const int64_t nb = (n_pairs - p0) < P.batch_pairs ? (n_pairs - p0) : P.batch_pairs;
-      ManaRowArgs A{};
-      A.psi = psi;
-      A.N = P.N;
-      A.nh = P.nh;
-      A.nhr = (uint32_t)pow3c(P.nh);
-      A.n_pairs = nb;
-      A.a0 = a0 + 2 * (uint64_t)p0;
-      A.a_end = a1;
-      A.exch = exch;
-      if constexpr (sizeof(T) == 4) e = launch_mana_row<T, 3, true>(P.nl, A, st);
-      else e = launch_mana_row<T, 2, true>(P.nl, A, st);
-      if (e) return e;
-      ManaColArgs C{};
-      C.exch = exch;
-      C.rowlen = (uint32_t)pow3c(P.nl);
-      C.n_pairs = nb;
-      C.acc = acc_col;
-      if constexpr (sizeof(T) == 4) e = launch_mana_col<T, 3>(P.nh, P.nl, C, st);
-      else e = launch_mana_col<T, 2>(P.nh, P.nl, C, st);
-      if (e) return e;
-    }
-    hipLaunchKernelGGL(k_mana_total, dim3(1), dim3(256), 0, st, acc_col, (int64_t)MANA_GRID, P.N, sums, out);
+    return hipPeekAtLastError() == hipSuccess ? OK : fail(E_HIP, "mana launch: %s", hipGetErrorString(hipGetLastError()));
   }
+  // Two-pass: batch k runs on lane k mod lanes (lane 0 = the caller's stream, lane 1 = the internal
+  // side stream, forked after the zeroing and joined before the totals), with that lane's exchange
+  // buffer and column accumulators, so lanes share no memory they write.
+  const size_t xb = align256((size_t)P.batch_pairs * (size_t)pow3c(P.N) * (P.dbl ? 16 : 8));
+  char *exch0 = w + accb * (1 + P.lanes);
+  const int64_t n_batches = (n_pairs + P.batch_pairs - 1) / P.batch_pairs;
+  const int L = (P.lanes > 1 && n_batches > 1) ? 2 : 1;
+  hipStream_t lst[2] = {st, st};
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  if (L == 2) {
+    if ((e = side_stream(&lst[1]))) return e;
+    if (hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ev_join, hipEventDisableTiming) != hipSuccess) {
+      if (ev_fork) (void)hipEventDestroy(ev_fork);
+      return fail(E_HIP, "mana: event creation failed");
+    }
+    if (hipEventRecord(ev_fork, st) != hipSuccess || hipStreamWaitEvent(lst[1], ev_fork, 0) != hipSuccess) {
+      (void)hipEventDestroy(ev_fork);
+      (void)hipEventDestroy(ev_join);
+      return fail(E_HIP, "mana: stream fork failed");
+    }
+  }
+  for (int64_t k = 0; k < n_batches && !e; ++k) {
+    const int l = (int)(k % L);
+    const int64_t p0 = k * P.batch_pairs;
+    const int64_t nb = (n_pairs - p0) < P.batch_pairs ? (n_pairs - p0) : P.batch_pairs;
+    ManaRowArgs A{};
+    A.psi = psi;
+    A.N = P.N;
+    A.nh = P.nh;
+    A.nhr = (uint32_t)pow3c(P.nh);
+    A.n_pairs = nb;
+    A.a0 = a0 + 2 * (uint64_t)p0;
+    A.a_end = a1;
+    A.exch = exch0 + (size_t)l * xb;
+    if constexpr (sizeof(T) == 4) e = launch_mana_row<T, 3, true>(P.nl, A, lst[l]);
+    else e = launch_mana_row<T, 2, true>(P.nl, A, lst[l]);
+    if (e) break;
+    ManaColArgs C{};
+    C.exch = A.exch;
+    C.rowlen = (uint32_t)pow3c(P.nl);
+    C.n_pairs = nb;
+    C.acc = acc_col + (size_t)l * MANA_GRID * 3;
+    if constexpr (sizeof(T) == 4) e = launch_mana_col<T, 3>(P.nh, P.nl, C, lst[l]);
+    else e = launch_mana_col<T, 2>(P.nh, P.nl, C, lst[l]);
+  }
+  if (L == 2) {
+    const bool ok = hipEventRecord(ev_join, lst[1]) == hipSuccess && hipStreamWaitEvent(st, ev_join, 0) == hipSuccess;
+    (void)hipEventDestroy(ev_fork);
+    (void)hipEventDestroy(ev_join);
+    if (!ok && !e) e = fail(E_HIP, "mana: stream join failed");
+  }
+  if (e) return e;
+  // fixed-order sum over the lanes' per-block accumulators (contiguous)
+  hipLaunchKernelGGL(k_mana_total, dim3(1), dim3(256), 0, st, acc_col, (int64_t)MANA_GRID * P.lanes, P.N, sums, out);
   return hipPeekAtLastError() == hipSuccess ? OK : fail(E_HIP, "mana launch: %s", hipGetErrorString(hipGetLastError()));
 }
 
-int mana_launch(int N, int dbl, int64_t batch, const void *psi, uint64_t a0, uint64_t a1, double *sums, double *out,
-                void *ws,
-                size_t ws_bytes, hipStream_t st) {
+int mana_launch(int N, int dbl, int64_t batch, int streams, const void *psi, uint64_t a0, uint64_t a1, double *sums,
+                double *out, void *ws, size_t ws_bytes, hipStream_t st) {
   ManaPlan P;
-  int e = mana_plan(N, dbl, batch, &P);
+  int e = mana_plan(N, dbl, batch, streams, &P);
   if (e) return e;
-  if (ws_bytes < mana_workspace(N, dbl, batch, a1 - a0)) return fail(E_WORKSPACE, "mana workspace too small");
+  if (ws_bytes < mana_workspace(N, dbl, batch, streams, a1 - a0)) return fail(E_WORKSPACE, "mana workspace too small");
   return dbl ? mana_t<double>(P, psi, a0, a1, sums, out, ws, st) : mana_t<float>(P, psi, a0, a1, sums, out, ws, st);
 }
 

@@ -68,19 +68,35 @@ def test_two_pass_n9_vs_oracle(orc, hm, c64):
     assert abs(got[0] - want[0]) <= TOL[c64] * max(1.0, abs(want[0])), (got, want)
 
 
+@pytest.mark.parametrize("streams", [1, 2])
 @pytest.mark.parametrize("batch", [7, 64])
-def test_two_pass_batches(orc, hm, batch):
+def test_two_pass_batches(orc, hm, batch, streams):
     """Launch batches of 7 shifts (rounded up to 4 shift pairs; ragged last launch) and of 64 at
-    n = 10, complex128."""
+    n = 10, complex128, on one stream or alternating over two."""
     n = 10
     psi = S.gaussian_state(n, d=3, seed=5020)
     x, w = gpu_state(psi, False)
     ctx = hm.Context()
     ctx.batch_shifts(batch)
-    say(f"[mana batch] n={n} batch={batch}")
+    ctx.set_option(hm.OPT_STREAMS, streams)
+    say(f"[mana batch] n={n} batch={batch} streams={streams}")
     got = hm.mana(x, ctx=ctx).cpu().numpy()
     want = orc.mana_fft(w)
     assert abs(got[0] - want[0]) <= 1e-10 * max(1.0, abs(want[0])), (got, want)
+
+
+@pytest.mark.parametrize("c64", [False, True])
+def test_one_and_two_streams_agree_at_n12(hm, c64):
+    """Full size: the two-stream plan and the one-stream plan (default) differ only in how the FP64
+    partial sums are grouped."""
+    x, _ = gpu_state(S.gaussian_state(12, d=3, seed=5012), c64)
+    two = hm.Context()
+    two.set_option(hm.OPT_STREAMS, 2)
+    say(f"[mana streams] n=12 c64={c64}")
+    a = hm.mana(x).cpu().numpy()
+    b = hm.mana(x, ctx=two).cpu().numpy()
+    np.testing.assert_allclose(a, b, rtol=1e-12, atol=0)
+    assert np.array_equal(b, hm.mana(x, ctx=two).cpu().numpy())  # deterministic
 
 
 def test_golden_values(hm):
