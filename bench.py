@@ -258,6 +258,8 @@ def main():
     ap.add_argument("--lds-split", type=int, default=0, choices=(0, 1, 2), help="HM_OPT_LDS_SPLIT")
     ap.add_argument("--row-bits", type=int, default=0, help="HM_OPT_ROW_BITS (0 = planner default)")
     ap.add_argument("--no-autotune", action="store_true", help="skip the plan autotuner (untimed, before warm-up)")
+    ap.add_argument("--grad-only", type=int, default=0, metavar="N",
+                    help="time only the fused forward + adjoint of M_2 at N qubits (profiling runs)")
     ap.add_argument("--mana-only", type=int, default=0, metavar="N",
                     help="profiling runs: time only the qutrit mana of an N-qutrit complex64 state per step")
     ap.add_argument("--oracle-table", action="store_true",
@@ -298,6 +300,25 @@ def main():
                           "unit": "phase-space points/s", "ms_per_step": ms, "steps": args.steps,
                           "config": {"workload": f"mana, N={n} qutrits, complex64 Gaussian state, seed 1212"},
                           "mana": float(o[0].item())}), flush=True)
+        return
+    if args.grad_only:
+        n = args.grad_only
+        import numpy as np
+        pg = S.ry_rz_cz_state(n, np.random.default_rng(4000 + n).uniform(0, 2 * math.pi, (2, 2, n)))
+        g = torch.from_numpy(S.to_c64_exact(pg)[0]).to(dev)
+        for _ in range(args.warmup):
+            hm.sre_grad(g, 2.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            o, _ = hm.sre_grad(g, 2.0)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        print(json.dumps({"metric": "Pauli expectations/s (fwd+grad M_2)", "value": 4.0 ** n / (ms * 1e-3),
+                          "unit": "Pauli expectations/s", "ms_per_step": ms, "steps": args.steps,
+                          "config": {"workload": f"fwd+grad M_2, N={n} qubits, complex64 2-layer RY/RZ + CZ "
+                                                 f"circuit state, seed {4000 + n}"},
+                          "M2": float(o[0].item())}), flush=True)
         return
     if args.copy_mib:
         n = args.copy_mib << 18  # float32 elements
