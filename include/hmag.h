@@ -51,7 +51,8 @@ typedef enum {
   HM_E_WORKSPACE = 4,   /* ws_bytes smaller than the size the matching *_workspace call gives   */
   HM_E_UNSUPPORTED = 5, /* valid request this build does not implement (message says what)    */
   HM_E_HIP = 6,         /* a HIP runtime call failed (message carries hipGetErrorString)       */
-  HM_E_ALIGN = 7        /* a pointer violates the alignment stated above                      */
+  HM_E_ALIGN = 7,       /* a pointer violates the alignment stated above                      */
+  HM_E_NOT_NORMALIZED = 8 /* HM_OPT_CHECK_NORM set and sum |psi|^2 off 1 (see HM_OPT_CHECK_NORM) */
 } hm_status;
 
 typedef enum { HM_C64 = 0, HM_C128 = 1 } hm_dtype;
@@ -89,6 +90,14 @@ const char *hm_version(void);
  *     exchange workspace).  Applies to SRE and mana (default 1 for both).  The FP64 partial
  *     sums of two-stream mana are grouped per stream, so its last bits differ from the
  *     one-stream result (each is deterministic).
+ *   HM_OPT_CHECK_NORM (0 or 1, default 0): every entry point that takes a state first computes
+ *     sum_x |psi_x|^2 in FP64 on the device, synchronises `stream` (so not usable under stream
+ *     capture) and returns HM_E_NOT_NORMALIZED, with nothing else enqueued, when it is off 1 by
+ *     more than 1e-5 (HM_C64) or 1e-12 (HM_C128).  The results assume a unit state (the paper's
+ *     problem statement; S_q scales as |psi|^{4q}); without the check the state is used as given
+ *     and lost_norm reports the deviation.  The check's two scalars (one device, one pinned host
+ *     double per device) are allocated by the library on first use and kept until the process
+ *     ends.
  * A combination outside the built kernels makes the SRE calls return HM_E_UNSUPPORTED. */
 typedef enum {
   HM_OPT_FORCE_PATH = 1,
@@ -98,7 +107,8 @@ typedef enum {
   HM_OPT_ROW_BITS = 5,
   HM_OPT_PIPELINE = 6,
   HM_OPT_LDS_SPLIT = 7,
-  HM_OPT_STREAMS = 8
+  HM_OPT_STREAMS = 8,
+  HM_OPT_CHECK_NORM = 9
 } hm_option;
 hm_status hm_set_option(hm_handle h, hm_option opt, int64_t value);
 

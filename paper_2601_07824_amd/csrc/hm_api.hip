@@ -60,6 +60,14 @@ static int check_ws(void *ws, size_t ws_bytes, size_t need) {
   return OK;
 }
 
+// HM_OPT_CHECK_NORM: the state's squared norm, checked on the device before anything is launched.
+static int norm_ok(hm_handle h, const void *psi, int d, int n, hm_dtype dtype, hipStream_t stream) {
+  if (!h->check_norm) return OK;
+  uint64_t D = 1;
+  for (int i = 0; i < n; ++i) D *= (uint64_t)d;
+  return check_norm(psi, D, dtype == HM_C128, stream);
+}
+
 static size_t psi_align(hm_dtype dt) { return dt == HM_C128 ? 16 : 8; }
 
 __global__ void k_fill(double *p, int64_t n, double v) {
@@ -108,6 +116,7 @@ const char *hm_status_string(hm_status s) {
     case HM_E_UNSUPPORTED: return "HM_E_UNSUPPORTED: not implemented for these arguments";
     case HM_E_HIP: return "HM_E_HIP: HIP runtime error";
     case HM_E_ALIGN: return "HM_E_ALIGN: misaligned pointer";
+    case HM_E_NOT_NORMALIZED: return "HM_E_NOT_NORMALIZED: state norm off 1 (HM_OPT_CHECK_NORM)";
   }
   return "unknown hm_status";
 }
@@ -149,6 +158,10 @@ hm_status hm_set_option(hm_handle h, hm_option opt, int64_t value) {
     case HM_OPT_STREAMS:
       if (value < 0 || value > 2) return (hm_status)fail(E_ARG, "HM_OPT_STREAMS %lld not in {0,1,2}", (long long)value);
       h->opts.streams = (int)value;
+      return HM_OK;
+    case HM_OPT_CHECK_NORM:
+      if (value < 0 || value > 1) return (hm_status)fail(E_ARG, "HM_OPT_CHECK_NORM %lld not in {0,1}", (long long)value);
+      h->check_norm = (int)value;
       return HM_OK;
   }
   return (hm_status)fail(E_ARG, "unknown option %d", (int)opt);
@@ -219,6 +232,7 @@ hm_status hm_sre(hm_handle h, const void *psi, int n, hm_dtype dtype, const doub
   HM_TRY(sre_plan(n, dtype == HM_C128, plan_opts(h, n, dtype == HM_C128), &p));
   const int64_t n_shifts = (int64_t)1 << n;
   HM_TRY(check_ws(ws, ws_bytes, sre_workspace(p, n_q, n_shifts)));
+  HM_TRY(norm_ok(h, psi, 2, n, dtype, stream));
   return (hm_status)sre_run(p, psi, qa, 0, nullptr, n_shifts, nullptr, nullptr, out, ws, stream);
 }
 
@@ -237,6 +251,7 @@ hm_status hm_sre_partial(hm_handle h, const void *psi, int n, hm_dtype dtype, co
   if (a0 > a1 || a1 > D) return (hm_status)fail(E_ARG, "shift range [%llu, %llu) not inside [0, 2^%d]", (unsigned long long)a0, (unsigned long long)a1, n);
   const int64_t n_slots = (int64_t)(a1 - a0);
   HM_TRY(check_ws(ws, ws_bytes, sre_workspace(p, n_q, n_slots)));
+  HM_TRY(norm_ok(h, psi, 2, n, dtype, stream));
   if (n_slots == 0) return (hm_status)fill_dev(sums, n_q + 1, 0.0, stream);
   return (hm_status)sre_run(p, psi, qa, a0, nullptr, n_slots, nullptr, sums, nullptr, ws, stream);
 }
@@ -266,6 +281,7 @@ hm_status hm_sre_rows(hm_handle h, const void *psi, int n, hm_dtype dtype, const
   HM_TRY(check_ptr(rows, 8, "rows"));
   HM_TRY(check_ptr(row_sums, 8, "row_sums"));
   HM_TRY(check_ws(ws, ws_bytes, sre_workspace(p, n_q, 0)));
+  HM_TRY(norm_ok(h, psi, 2, n, dtype, stream));
   return (hm_status)sre_run(p, psi, qa, 0, rows, n_rows, row_sums, nullptr, nullptr, ws, stream);
 }
 
@@ -279,6 +295,7 @@ hm_status hm_sre_row_values(hm_handle h, const void *psi, int n, hm_dtype dtype,
   HM_TRY(check_ptr(out, 8, "out"));
   if (a >> n) return (hm_status)fail(E_ARG, "a = %llu is not an %d-bit X-string", (unsigned long long)a, n);
   HM_TRY(check_ws(ws, ws_bytes, sre_row_values_workspace(n, dtype == HM_C128)));
+  HM_TRY(norm_ok(h, psi, 2, n, dtype, stream));
   return (hm_status)sre_row_values_launch(n, dtype == HM_C128, psi, a, out, ws, stream);
 }
 
@@ -296,6 +313,7 @@ hm_status hm_sre_grad(hm_handle h, const void *psi, int n, hm_dtype dtype, doubl
   size_t need = 0;
   HM_TRY(sre_grad_workspace(o, n, dtype == HM_C128, &need));
   HM_TRY(check_ws(ws, ws_bytes, need));
+  HM_TRY(norm_ok(h, psi, 2, n, dtype, stream));
   return (hm_status)sre_grad_launch(o, n, dtype == HM_C128, psi, q, out, grad, ws, ws_bytes, stream);
 }
 
@@ -317,6 +335,7 @@ hm_status hm_sre_grad_batched(hm_handle h, const void *const *psis, int n, int b
   size_t need = 0;
   HM_TRY(sre_grad_batched_workspace(o, n, dtype == HM_C128, batch, &need));
   HM_TRY(check_ws(ws, ws_bytes, need));
+  for (int s = 0; s < batch; ++s) HM_TRY(norm_ok(h, psis[s], 2, n, dtype, stream));
   return (hm_status)sre_grad_batched_launch(o, n, dtype == HM_C128, psis, batch, q, out, grads, ws, ws_bytes, stream);
 }
 
@@ -364,6 +383,7 @@ hm_status hm_sre_batched(hm_handle h, const void *const *psis, const int *ns, in
   HM_TRY(batched_ws(h, ns, batch, dbl, n_q, &need));
   for (int i = 0; i < batch; ++i) HM_TRY(check_ptr(psis[i], psi_align(dtype), "psis[i]"));
   HM_TRY(check_ws(ws, ws_bytes, need));
+  for (int i = 0; i < batch; ++i) HM_TRY(norm_ok(h, psis[i], 2, ns[i], dtype, stream));
   // size classes in order of first appearance; resident classes go up to HM_BATCH_PTRS per launch
   std::vector<char> done(batch, 0);
   for (int i = 0; i < batch; ++i) {
@@ -410,6 +430,7 @@ hm_status hm_sre_sampled(hm_handle h, const void *psi, int n, hm_dtype dtype, co
   HM_TRY(sre_plan(n, dtype == HM_C128, plan_opts(h, n, dtype == HM_C128), &p));
   const size_t rs_bytes = align256((size_t)(n_rows + 1) * 2 * sizeof(double));
   HM_TRY(check_ws(ws, ws_bytes, rs_bytes + sre_workspace(p, 1, 0)));
+  HM_TRY(norm_ok(h, psi, 2, n, dtype, stream));
   double *rs = (double *)ws;
   double *s0 = rs + 2 * n_rows;  // exact row a = 0
   HM_TRY(sre_run(p, psi, qa, 0, nullptr, 1, s0, nullptr, nullptr, (char *)ws + rs_bytes, stream));
@@ -470,6 +491,7 @@ hm_status hm_mana(hm_handle h, const void *psi, int n, hm_dtype dtype, double *o
   uint64_t D = 1;
   for (int i = 0; i < n; ++i) D *= 3;
   HM_TRY(check_ws(ws, ws_bytes, mana_workspace(n, dtype == HM_C128, h->opts.batch, (int)h->opts.streams, D)));
+  HM_TRY(norm_ok(h, psi, 3, n, dtype, stream));
   return (hm_status)mana_launch(n, dtype == HM_C128, h->opts.batch, (int)h->opts.streams, psi, 0, D, nullptr, out, ws, ws_bytes, stream);
 }
 
@@ -485,6 +507,7 @@ hm_status hm_mana_partial(hm_handle h, const void *psi, int n, hm_dtype dtype, u
   for (int i = 0; i < n; ++i) D *= 3;
   if (a0 > a1 || a1 > D) return (hm_status)fail(E_ARG, "shift range [%llu, %llu) not inside [0, 3^%d]", (unsigned long long)a0, (unsigned long long)a1, n);
   HM_TRY(check_ws(ws, ws_bytes, mana_workspace(n, dtype == HM_C128, h->opts.batch, (int)h->opts.streams, a1 - a0)));
+  HM_TRY(norm_ok(h, psi, 3, n, dtype, stream));
   if (a1 == a0) return (hm_status)fill_dev(sums, 3, 0.0, stream);
   return (hm_status)mana_launch(n, dtype == HM_C128, h->opts.batch, (int)h->opts.streams, psi, a0, a1, sums, nullptr, ws, ws_bytes, stream);
 }

@@ -17,7 +17,10 @@ namespace hm {
 struct QArgs;
 
 // Status codes mirror hm_status in include/hmag.h.
-enum Status { OK = 0, E_ARG = 1, E_DTYPE = 2, E_SIZE = 3, E_WORKSPACE = 4, E_UNSUPPORTED = 5, E_HIP = 6, E_ALIGN = 7 };
+enum Status {
+  OK = 0, E_ARG = 1, E_DTYPE = 2, E_SIZE = 3, E_WORKSPACE = 4, E_UNSUPPORTED = 5, E_HIP = 6, E_ALIGN = 7,
+  E_NOT_NORMALIZED = 8
+};
 
 // Records a formatted message for hm_last_error() and returns st.
 int fail(int st, const char *fmt, ...);
@@ -109,6 +112,7 @@ struct TunedPlan {
 struct hm_context {
   hm::PlanOpts opts;
   std::vector<hm::TunedPlan> tuned;
+  int check_norm = 0;  // HM_OPT_CHECK_NORM
 };
 
 namespace hm {
@@ -160,6 +164,11 @@ int sre_pipe_f64(const SrePlan &p, const void *psi, const QArgs &qa, uint64_t a0
 // Row values <P_{a,b}> of one X-row (unfolded FWHT of one row).
 int sre_row_values_launch(int N, int dbl, const void *psi, uint64_t a, double *out, void *ws, hipStream_t stream);
 size_t sre_row_values_workspace(int N, int dbl);
+
+// ---- input checks ----------------------------------------------------------------------------
+// Squared norm of a state of D amplitudes on the device; synchronises `stream`; E_NOT_NORMALIZED
+// when it is off 1 by more than 1e-5 (FP32) / 1e-12 (FP64).
+int check_norm(const void *psi, uint64_t D, int dbl, hipStream_t stream);
 
 // ---- SRE gradient ----------------------------------------------------------------------------
 // Workgroup-resident kernel up to n = 13 (FP32) / 12 (FP64), two-pass kernels (default split)

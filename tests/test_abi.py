@@ -12,7 +12,7 @@ import paper_2601_07824_amd as hm
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "hmag.h")
 
-HM_OK, HM_E_ARG, HM_E_DTYPE, HM_E_SIZE, HM_E_WORKSPACE, HM_E_UNSUPPORTED, HM_E_HIP, HM_E_ALIGN = range(8)
+HM_OK, HM_E_ARG, HM_E_DTYPE, HM_E_SIZE, HM_E_WORKSPACE, HM_E_UNSUPPORTED, HM_E_HIP, HM_E_ALIGN, HM_E_NOT_NORMALIZED = range(9)
 P = ctypes.c_void_p
 
 
@@ -45,7 +45,7 @@ def test_every_declared_symbol_is_exported_and_bound(L):
 
 def test_version_and_status_strings(L):
     assert b"gfx950" in L.hm_version()
-    for s in range(8):
+    for s in range(9):
         assert L.hm_status_string(s).startswith(b"HM_")
 
 
@@ -261,3 +261,12 @@ def test_batched_gradient_workspace_and_errors(L, h):
     assert L.hm_sre_grad_batched(h, ptrs, 8, 2, 0, 2.0, out, ptrs, ws, 16, None) == HM_E_WORKSPACE
     bad = (P * 2)(good, P(0x100004))  # misaligned second state
     assert L.hm_sre_grad_batched(h, bad, 8, 2, 0, 2.0, out, ptrs, ws, 1 << 30, None) == HM_E_ALIGN
+
+
+def test_check_norm_option(L, h):
+    assert L.hm_set_option(h, 9, 2) == HM_E_ARG
+    assert L.hm_set_option(h, 9, -1) == HM_E_ARG
+    assert L.hm_set_option(h, 9, 1) == HM_OK
+    # argument errors still come first, before any device work
+    assert L.hm_sre(h, None, 8, 0, q_arr(2.0), 1, P(0x100000), P(0x200000), 1 << 30, None) == HM_E_ARG
+    assert L.hm_set_option(h, 9, 0) == HM_OK
