@@ -25,9 +25,6 @@ def cases():
         yield (f"sre_clifford_t_n16_k{k}_seed42{k:02d}_c64",
                (lambda k=k: S.to_c64_exact(S.clifford_t_state(16, k, seed=4200 + k))[1]), "sre", [2.0])
     yield ("mana_gauss_n8_seed5008_c128", lambda: S.gaussian_state(8, d=3, seed=5008), "mana", None)
-    # the benchmark state (n = 20, brick-wall depth 40, seed 2020), complex64 values
-    yield ("sre_brickwall_n20_d40_seed2020_c64", lambda: S.to_c64_exact(S.brickwall_haar(20, 40, seed=2020))[1], "sre",
-           [2.0])
     yield ("mana_gauss_n10_seed5010_c64", lambda: S.to_c64_exact(S.gaussian_state(10, d=3, seed=5010))[1], "mana", None)
 
 

@@ -52,9 +52,10 @@ def batch_states(n, B, c64, seed):
     return torch.from_numpy(np.stack(rows)).to(_dev()), exact
 
 
-# (n, complex64, batch): resident sizes (one launch per 64 states, 70 = 64 + 6), and n = 14, which
-# runs the two-pass kernels state after state on one workspace.
-CASES = [(3, False, 2), (6, True, 5), (9, False, 7), (12, True, 64), (12, False, 9), (13, True, 70), (14, True, 3)]
+# (n, complex64, batch): resident sizes (one launch per 64 states, 70 = 64 + 6), and complex64
+# n = 14 / complex128 n = 13, which run the two-pass kernels state after state on one workspace.
+CASES = [(3, False, 2), (6, True, 5), (9, False, 7), (12, True, 64), (12, False, 9), (13, True, 70), (14, True, 3),
+         (13, False, 3)]
 
 
 @pytest.mark.parametrize("n,c64,B", CASES)
