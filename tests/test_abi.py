@@ -270,3 +270,37 @@ def test_check_norm_option(L, h):
     # argument errors still come first, before any device work
     assert L.hm_sre(h, None, 8, 0, q_arr(2.0), 1, P(0x100000), P(0x200000), 1 << 30, None) == HM_E_ARG
     assert L.hm_set_option(h, 9, 0) == HM_OK
+
+
+def test_header_is_plain_c_and_links(tmp_path):
+    """include/hmag.h compiles as C99 (plain C types only) and a C program links against libhmag.so
+    and calls it (no device work: version, status strings, handle, argument errors)."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    src = tmp_path / "use_hmag.c"
+    src.write_text(r'''
+#include "hmag.h"
+#include <stdio.h>
+#include <string.h>
+int main(void) {
+  hm_handle h = NULL;
+  if (hm_create(&h) != HM_OK) return 1;
+  double q = 2.0, out[2];
+  hm_status s = hm_sre(h, NULL, 8, HM_C64, &q, 1, out, NULL, 0, NULL);
+  printf("%s|%s|%s\n", hm_version(), hm_status_string(s), hm_last_error());
+  if (s != HM_E_ARG) return 2;
+  if (hm_set_option(h, HM_OPT_CHECK_NORM, 1) != HM_OK) return 3;
+  return hm_destroy(h) == HM_OK ? 0 : 4;
+}
+''')
+    exe = tmp_path / "use_hmag"
+    libdir = os.path.dirname(hm.lib_path)
+    cmd = [gcc, "-std=c99", "-Wall", "-Werror", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
+           "-I", "/opt/rocm/include", str(src), "-L", libdir, "-lhmag", f"-Wl,-rpath,{libdir}", "-o", str(exe)]
+    subprocess.run(cmd, check=True, capture_output=True, text=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, (r.returncode, r.stdout, r.stderr)
+    assert "gfx950" in r.stdout and "HM_E_ARG" in r.stdout
