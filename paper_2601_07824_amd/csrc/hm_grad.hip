@@ -177,23 +177,27 @@ __global__ __launch_bounds__((1 << (NL - RB)) < 64 ? 64 : (1 << (NL - RB))) void
 }
 
 // totals over blocks -> out = {M_q, lost_norm}; scale = 2 / ((1 - q) S_q ln 2) for the gradient.
-// Workgroup s handles state s: spart[s][nblk][2] -> out[2 s .. 2 s + 1], scale[s].
-__global__ __launch_bounds__(256) void k_grad_totals(const double *spart, int nblk, int N, double q, double *out,
-                                                    double *scale) {
-  __shared__ double r1[256], rq[256];
+// Workgroup s handles state s: spart[s][nblk][2] -> out[2 s .. 2 s + 1], scale[s].  Fixed order:
+// thread t sums entries t, t + TOT_T, ... in turn, then a tree over the threads.
+static constexpr int TOT_T = 1024;
+__global__ __launch_bounds__(TOT_T) void k_grad_totals(const double *spart, int nblk, int N, double q, double *out,
+                                                      double *scale) {
+  __shared__ double r1[TOT_T], rq[TOT_T];
   const uint32_t t = threadIdx.x;
-  spart += (size_t)blockIdx.x * 2 * nblk;
+  const double2 *sp = (const double2 *)spart + (size_t)blockIdx.x * nblk;
   out += 2 * blockIdx.x;
   scale += blockIdx.x;
   double a = 0.0, b = 0.0;
-  for (int i = t; i < nblk; i += 256) {
-    a += spart[2 * i];
-    b += spart[2 * i + 1];
+#pragma unroll 4
+  for (int i = t; i < nblk; i += TOT_T) {
+    const double2 v = sp[i];
+    a += v.x;
+    b += v.y;
   }
   r1[t] = a;
   rq[t] = b;
   __syncthreads();
-  for (uint32_t w = 128; w > 0; w >>= 1) {
+  for (uint32_t w = TOT_T / 2; w > 0; w >>= 1) {
     if (t < w) {
       r1[t] += r1[t + w];
       rq[t] += rq[t + w];
@@ -302,7 +306,7 @@ int sre_grad_workspace(const PlanOpts &o, int N, int dbl, size_t *bytes) {
 
 int grad_totals_launch(const double *shift_sums, int64_t n_shifts, int N, double q, double *out, double *scale,
                        hipStream_t st) {
-  hipLaunchKernelGGL(k_grad_totals, dim3(1), dim3(256), 0, st, shift_sums, (int)n_shifts, N, q, out, scale);
+  hipLaunchKernelGGL(k_grad_totals, dim3(1), dim3(TOT_T), 0, st, shift_sums, (int)n_shifts, N, q, out, scale);
   return hipPeekAtLastError() == hipSuccess ? OK : fail(E_HIP, "gradient totals: %s", hipGetErrorString(hipGetLastError()));
 }
 
@@ -353,7 +357,7 @@ static int grad_t(int N, const void *const *psis, int states, double q, double *
       return fail(E_SIZE, "gradient: n = %d above the workgroup-resident limit %d", N, grad_max_n(sizeof(T) == 8));
   }
 #undef HM_G
-  hipLaunchKernelGGL(k_grad_totals, dim3(states), dim3(256), 0, st, A.spart, nblk, N, q, out, scale);
+  hipLaunchKernelGGL(k_grad_totals, dim3(states), dim3(TOT_T), 0, st, A.spart, nblk, N, q, out, scale);
   const int64_t n = (int64_t)1 << N;
   hipLaunchKernelGGL(k_grad_reduce<T>, dim3((unsigned)((n + 255) / 256), states), dim3(256), 0, st,
                      (const vec2<T> *)A.gpart, nblk, n, (const double *)scale, G);
