@@ -266,9 +266,10 @@ static int grad2_plan(const PlanOpts &o, int N, int dbl, SrePlan *p) {
   if (e) return e;
   if (p->nf < 11 || p->nf > 19) return fail(E_UNSUPPORTED, "gradient: two-pass kernels cover n in [12, 20] (n = %d)", N);
   if (o.batch) return OK;
-  if (N <= 16) {
-    // Up to n = 16 a batch of 2^nl shifts is a small launch (2^nl <= 256): take 256 MiB (FP32) /
-    // 128 MiB (FP64) exchange batches through the separate backward-row and accumulation kernels.
+  if (p->nl <= 7) {
+    // Rows of at most 2^7 (n <= 15): a batch of 2^nl shifts is a small launch, so take 256 MiB
+    // (FP32) / 128 MiB (FP64) exchange batches through the separate backward-row and accumulation
+    // kernels (n = 14: 1.5 against 3.4 ms; at n = 16 the fused 2^8-shift batches are 3 % faster).
     const int64_t want = ((int64_t)(dbl ? 128 : 256) << 20) / (((int64_t)1 << p->nf) * (dbl ? 16 : 8));
     const int64_t all = (int64_t)1 << N;
     g.batch = want < all ? want : all;

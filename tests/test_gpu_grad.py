@@ -139,9 +139,9 @@ def test_grad_determinism(hm):
                                           (True, 14, False), (False, 14, False)])
 def test_grad_two_pass_vs_fwht_oracle(orc, hm, c64, n, forced, batch):
     """batch 96: unaligned batches (backward row pass and accumulation as separate kernels, last batch
-    ragged); default batches (up to n = 16 large batches through the separate kernels); batch 64
+    ragged); default batches (up to n = 15 large batches through the separate kernels); batch 64
     (aligned, at most 2^nl shifts: the fused backward-row + accumulation kernel for every batch after
-    the first, the default above n = 16)."""
+    the first, the default from n = 16 on)."""
     psi = S.ry_rz_cz_state(n, np.random.default_rng(6600 + n).uniform(0, 2 * math.pi, (2, 2, n)))
     x, w = gpu_state(psi, c64)
     ctx = hm.Context()
