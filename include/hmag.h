@@ -49,7 +49,7 @@ typedef enum {
   HM_E_DTYPE = 2,       /* dtype not HM_C64 / HM_C128                                          */
   HM_E_SIZE = 3,        /* n outside the supported range for this entry point                  */
   HM_E_WORKSPACE = 4,   /* ws_bytes smaller than the size the matching *_workspace call gives   */
-  HM_E_UNSUPPORTED = 5, /* valid request this build does not implement (message says what)    */
+  HM_E_UNSUPPORTED = 5, /* valid request the library does not implement (message says what)   */
   HM_E_HIP = 6,         /* a HIP runtime call failed (message carries hipGetErrorString)       */
   HM_E_ALIGN = 7,       /* a pointer violates the alignment stated above                      */
   HM_E_NOT_NORMALIZED = 8 /* HM_OPT_CHECK_NORM set and sum |psi|^2 off 1 (see HM_OPT_CHECK_NORM) */
@@ -65,7 +65,7 @@ hm_status hm_destroy(hm_handle h);
 const char *hm_status_string(hm_status s);
 /* Message describing the most recent failure on the calling thread ("" if none). */
 const char *hm_last_error(void);
-/* Version string of this build. */
+/* Version string of the library (names the target, gfx950). */
 const char *hm_version(void);
 
 /* Options (testing and tuning); 0 always means "automatic".
