@@ -129,3 +129,14 @@ def test_autograd_batched_circuits(orc, hm):
         say(f"[grad autograd batched] state {i} angle {idx}: fd={fd:.8e} an={an:.8e}")
         # complex64 states: the FP32 forward limits the agreement to about 1e-5 relative
         assert abs(an - fd) < 1e-4 * max(1.0, abs(fd)), (i, idx, an, fd)
+
+
+@pytest.mark.parametrize("n,c64", [(8, True), (13, True), (12, False), (15, True)])
+def test_batch_of_one_is_the_single_call(hm, n, c64):
+    """A batch of one state runs exactly the single-state launch: bitwise equal results."""
+    X, _ = batch_states(n, 1, c64, seed=7600 + n)
+    say(f"[grad batched] batch of one n={n} c64={c64}")
+    out, G = hm.sre_grad_batched(X, 2.0)
+    o1, g1 = hm.sre_grad(X[0], 2.0)
+    assert np.array_equal(out[0].cpu().numpy(), o1.cpu().numpy())
+    assert np.array_equal(G[0].cpu().numpy(), g1.cpu().numpy())
