@@ -409,3 +409,23 @@ def test_clifford_t_n16_vs_golden(hm, k):
         got = hm.sre(t.to(_dev()), (2.0,)).cpu().numpy()
         assert abs(got[0] - want[0]) < tol * max(1.0, abs(want[0])), (got, want)
         assert abs(got[1] - want[1]) < (1e-6 if tol > 1e-9 else 1e-12), (got, want)
+
+
+def test_sharded_evaluation_n20(hm):
+    """The multi-GPU plan on one GPU: the X-shifts of the N = 20 bench state split into 8 equal
+    shards (one per prospective GPU), hm_sre_partial on each, the partial sums added in shard order
+    (what one all-reduce would do) and finalised with hm_sre_finalize, against the single call.
+    The sums differ only in FP64 grouping."""
+    n, G = 20, 8
+    v, _ = S.to_c64_exact(S.brickwall_haar(n, 2 * n, seed=2020))
+    x = torch.from_numpy(v).to(_dev())
+    q = (2.0,)
+    say("[sre sharded] n=20, 8 shards")
+    parts = [hm.sre_partial(x, q, r * (2 ** n // G), (r + 1) * (2 ** n // G)) for r in range(G)]
+    total = parts[0].clone()
+    for p in parts[1:]:
+        total += p
+    got = hm.sre_finalize(n, q, total).cpu().numpy()
+    want = hm.sre(x, q).cpu().numpy()
+    assert abs(got[0] - want[0]) < 1e-12 * abs(want[0]), (got, want)
+    assert abs(got[1] - want[1]) < 1e-12, (got, want)
