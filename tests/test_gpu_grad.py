@@ -243,3 +243,19 @@ def test_grad_maximum_size_identities(hm):
     assert abs(ip.real - want) < 1e-4 * abs(want) and abs(ip.imag) < 1e-4 * abs(want), ip
     m = hm.sre(x, (2.0,)).cpu().numpy()
     assert abs(out.cpu().numpy()[0] - m[0]) < 1e-5 * abs(m[0])
+
+
+@pytest.mark.parametrize("c64,n,forced", [(False, 5, False), (True, 9, False), (False, 13, True), (True, 14, False)])
+def test_grad_fractional_q(orc, hm, c64, n, forced):
+    """q = 1.5 (the general |chi|^{2q-2} chi seed, no integer shortcut) on the resident and two-pass
+    kernels against the FP64 oracle gradient."""
+    psi = S.gaussian_state(n, seed=6800 + n)
+    x, w = gpu_state(psi, c64)
+    ctx = hm.Context()
+    if forced:
+        ctx.force_path(2)
+    say(f"[grad q=1.5] n={n} c64={c64} forced={forced}")
+    out, g = hm.sre_grad(x, 1.5, ctx=ctx)
+    want_out, want_g = orc.sre_grad_direct(w, 1.5) if n <= 7 else orc.sre_grad_fwht(w, 1.5)
+    assert rel_l2(g.cpu().numpy().astype(np.complex128), want_g) < (1e-4 if c64 else 1e-9)
+    np.testing.assert_allclose(out.cpu().numpy(), want_out, rtol=(1e-5 if c64 else 1e-11), atol=1e-6 if c64 else 1e-12)

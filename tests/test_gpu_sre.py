@@ -429,3 +429,21 @@ def test_sharded_evaluation_n20(hm):
     want = hm.sre(x, q).cpu().numpy()
     assert abs(got[0] - want[0]) < 1e-12 * abs(want[0]), (got, want)
     assert abs(got[1] - want[1]) < 1e-12, (got, want)
+
+
+@pytest.mark.parametrize("c64", [False, True])
+def test_two_pass_eight_renyi_indices(orc, hm, c64):
+    """The largest q list (8 indices, fractional, q = 1 and large q) through the two-pass kernels'
+    general-q accumulation, ragged batches, against Algorithm 2 on the CPU."""
+    n = 12
+    q = (0.5, 1.0, 1.5, 2.0, 2.5, 3.0, 4.0, 8.0)
+    ctx = hm.Context()
+    ctx.force_path(2)
+    ctx.batch_shifts(37)
+    psi = S.brickwall_haar(n, 2 * n, seed=3900)
+    x, w = gpu_state(psi, c64)
+    say(f"[sre two-pass 8 q] c64={c64}")
+    got = hm.sre(x, q, ctx=ctx).cpu().numpy()
+    want = orc.sre_fwht(w, q)
+    assert rel_err(got[:-1], want[:-1]) < TOL[c64], (got, want)
+    assert abs(got[-1] - want[-1]) < (1e-12 if not c64 else 2e-6)
