@@ -213,24 +213,40 @@ __global__ __launch_bounds__(TOT_T) void k_grad_totals(const double *spart, int 
 }
 
 // grad_s[y] = scale[s] * sum over blocks of G partials (fixed order); blockIdx.y = state s.
+// A workgroup takes 64 consecutive y (one per lane, coalesced) x 16 groups of partials (one per
+// wave): wave k sums partials k, k + 16, ... in turn, then wave 0 adds the 16 group sums in order.
+static constexpr int RED_Y = 64, RED_G = 16;
 template <typename T>
-__global__ void k_grad_reduce(const vec2<T> *gpart, int nblk, int64_t n, const double *scale, GradOuts outs) {
-  const int64_t y = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (y >= n) return;
-  vec2<T> *grad = (vec2<T> *)outs.g[blockIdx.y];
+__global__ __launch_bounds__(RED_Y *RED_G) void k_grad_reduce(const vec2<T> *gpart, int nblk, int64_t n,
+                                                              const double *scale, GradOuts outs) {
+  __shared__ double sr[RED_G][RED_Y], si[RED_G][RED_Y];
+  const uint32_t ly = threadIdx.x % RED_Y, g = threadIdx.x / RED_Y;
+  const int64_t y = (int64_t)blockIdx.x * RED_Y + ly;
   gpart += (size_t)blockIdx.y * nblk * n;
-  scale += blockIdx.y;
   double gr = 0.0, gi = 0.0;
-  for (int b = 0; b < nblk; ++b) {
-    const vec2<T> v = gpart[(size_t)b * n + y];
-    gr += (double)v.x;
-    gi += (double)v.y;
+  if (y < n) {
+    for (int b = (int)g; b < nblk; b += RED_G) {
+      const vec2<T> v = gpart[(size_t)b * n + y];
+      gr += (double)v.x;
+      gi += (double)v.y;
+    }
   }
-  const double s = scale[0];
-  vec2<T> o;
-  o.x = (T)(s * gr);
-  o.y = (T)(s * gi);
-  grad[y] = o;
+  sr[g][ly] = gr;
+  si[g][ly] = gi;
+  __syncthreads();
+  if (g == 0 && y < n) {
+    double tr = 0.0, ti = 0.0;
+#pragma unroll
+    for (int k = 0; k < RED_G; ++k) {
+      tr += sr[k][ly];
+      ti += si[k][ly];
+    }
+    const double sc = scale[blockIdx.y];
+    vec2<T> o;
+    o.x = (T)(sc * tr);
+    o.y = (T)(sc * ti);
+    ((vec2<T> *)outs.g[blockIdx.y])[y] = o;
+  }
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -360,7 +376,7 @@ static int grad_t(int N, const void *const *psis, int states, double q, double *
 #undef HM_G
   hipLaunchKernelGGL(k_grad_totals, dim3(states), dim3(TOT_T), 0, st, A.spart, nblk, N, q, out, scale);
   const int64_t n = (int64_t)1 << N;
-  hipLaunchKernelGGL(k_grad_reduce<T>, dim3((unsigned)((n + 255) / 256), states), dim3(256), 0, st,
+  hipLaunchKernelGGL(k_grad_reduce<T>, dim3((unsigned)((n + RED_Y - 1) / RED_Y), states), dim3(RED_Y * RED_G), 0, st,
                      (const vec2<T> *)A.gpart, nblk, n, (const double *)scale, G);
   return hipPeekAtLastError() == hipSuccess ? OK : fail(E_HIP, "gradient launch: %s", hipGetErrorString(hipGetLastError()));
 }

@@ -313,20 +313,38 @@ __global__ __launch_bounds__(256) void k_grad_accum(AccumArgs A) {
   }
 }
 
+// grad[y] = scale * sum over the groups' partials: a workgroup takes 64 consecutive y (one per lane)
+// x 16 strided sets of groups (one per wave), then wave 0 adds the 16 set sums in order.
 template <typename T>
-__global__ void k_grad2_final(const double2 *gpart, int groups, int64_t n, const double *scale, vec2<T> *grad) {
-  const int64_t y = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (y >= n) return;
+__global__ __launch_bounds__(1024) void k_grad2_final(const double2 *gpart, int groups, int64_t n, const double *scale,
+                                                      vec2<T> *grad) {
+  constexpr int FY = 64, FG = 16;
+  __shared__ double sr[FG][FY], si[FG][FY];
+  const uint32_t ly = threadIdx.x % FY, g = threadIdx.x / FY;
+  const int64_t y = (int64_t)blockIdx.x * FY + ly;
   double gr = 0.0, gi = 0.0;
-  for (int g = 0; g < groups; ++g) {
-    const double2 v = gpart[(size_t)g * n + y];
-    gr += v.x;
-    gi += v.y;
+  if (y < n) {
+    for (int k = (int)g; k < groups; k += FG) {
+      const double2 v = gpart[(size_t)k * n + y];
+      gr += v.x;
+      gi += v.y;
+    }
   }
-  vec2<T> o;
-  o.x = (T)(scale[0] * gr);
-  o.y = (T)(scale[0] * gi);
-  grad[y] = o;
+  sr[g][ly] = gr;
+  si[g][ly] = gi;
+  __syncthreads();
+  if (g == 0 && y < n) {
+    double tr = 0.0, ti = 0.0;
+#pragma unroll
+    for (int k = 0; k < FG; ++k) {
+      tr += sr[k][ly];
+      ti += si[k][ly];
+    }
+    vec2<T> o;
+    o.x = (T)(scale[0] * tr);
+    o.y = (T)(scale[0] * ti);
+    grad[y] = o;
+  }
 }
 
 __global__ void k_zero2(double2 *p, int64_t n) {
@@ -523,7 +541,7 @@ int grad2_t(const SrePlan &p, const void *psi, double q, double *out, void *grad
   }
   int e = grad_totals_launch(shift_sums, n_shifts, N, q, out, scale, st);
   if (e) return e;
-  hipLaunchKernelGGL(k_grad2_final<T>, dim3((unsigned)((n_shifts + 255) / 256)), dim3(256), 0, st,
+  hipLaunchKernelGGL(k_grad2_final<T>, dim3((unsigned)((n_shifts + 63) / 64)), dim3(1024), 0, st,
                      (const double2 *)gpart, groups, n_shifts, (const double *)scale, (vec2<T> *)grad);
   return hipPeekAtLastError() == hipSuccess ? OK
                                             : fail(E_HIP, "two-pass gradient launch: %s", hipGetErrorString(hipGetLastError()));
