@@ -125,23 +125,35 @@ __global__ __launch_bounds__(256) void k_sre_sampled_stats(const double *row_sum
   }
 }
 
-// Fixed-order sum over all per-shift sums; optionally finalise (Eq. sre).
-__global__ __launch_bounds__(256) void k_sre_total(const double *shift_sums, int64_t n_slots, int nacc, QArgs qa,
-                                                   int N, double *sums, double *out) {
-  __shared__ double red[256];
+// Fixed-order sum over all per-shift sums; optionally finalise (Eq. sre).  Thread t adds the rows
+// t, t + TOT_NT, ... (all nacc slots of a row at once), then a tree over the threads per slot.
+static constexpr int TOT_NT = 1024;
+__global__ __launch_bounds__(TOT_NT) void k_sre_total(const double *shift_sums, int64_t n_slots, int nacc, QArgs qa,
+                                                      int N, double *sums, double *out) {
+  __shared__ double red[TOT_NT];
   __shared__ double tot[HM_MAX_Q + 1];
   const uint32_t t = threadIdx.x;
-  for (int k = 0; k < nacc; ++k) {
-    double s = 0.0;
-    for (int64_t i = t; i < n_slots; i += 256) s += shift_sums[i * nacc + k];
-    red[t] = s;
-    __syncthreads();
-    for (uint32_t w = 128; w > 0; w >>= 1) {
-      if (t < w) red[t] += red[t + w];
+  double s[HM_MAX_Q + 1];
+#pragma unroll
+  for (int k = 0; k <= HM_MAX_Q; ++k) s[k] = 0.0;
+  for (int64_t i = t; i < n_slots; i += TOT_NT) {
+    const double *row = shift_sums + i * nacc;
+#pragma unroll
+    for (int k = 0; k <= HM_MAX_Q; ++k)
+      if (k < nacc) s[k] += row[k];
+  }
+#pragma unroll
+  for (int k = 0; k <= HM_MAX_Q; ++k) {
+    if (k < nacc) {  // uniform across the workgroup
+      red[t] = s[k];
+      __syncthreads();
+      for (uint32_t w = TOT_NT / 2; w > 0; w >>= 1) {
+        if (t < w) red[t] += red[t + w];
+        __syncthreads();
+      }
+      if (t == 0) tot[k] = red[0];
       __syncthreads();
     }
-    if (t == 0) tot[k] = red[0];
-    __syncthreads();
   }
   if (t == 0) {
     if (sums)
@@ -276,7 +288,7 @@ int sre_run(const SrePlan &p, const void *psi, const QArgs &qa, uint64_t a0, con
 int sre_reduce_shifts(const double *shift_sums, int64_t n_slots, const QArgs &qa, int N, double *sums, double *out,
                       hipStream_t st) {
   ProfScope prof("sre_total", st);
-  hipLaunchKernelGGL(k_sre_total, dim3(1), dim3(256), 0, st, shift_sums, n_slots, nacc_of(qa), qa, N, sums, out);
+  hipLaunchKernelGGL(k_sre_total, dim3(1), dim3(TOT_NT), 0, st, shift_sums, n_slots, nacc_of(qa), qa, N, sums, out);
   return hipPeekAtLastError() == hipSuccess ? OK : fail(E_HIP, "SRE reduce launch: %s", hipGetErrorString(hipGetLastError()));
 }
 
