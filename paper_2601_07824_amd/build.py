@@ -1,6 +1,7 @@
 """Build libhmag.so (HIP kernels + C-ABI) for gfx950 with hipcc, in-tree.
 
-Usage: python -m paper_2601_07824_amd.build  (or call build()).  Every call recompiles.
+Usage: python -m paper_2601_07824_amd.build [--changed]  (or call build()).  Every call recompiles
+everything unless --changed (only_changed=True) is given.
 """
 from __future__ import annotations
 
@@ -21,8 +22,18 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-ta
          "-packed-fp32-ops", "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas"]
 
 
-def _compile(src: str) -> str:
+def _stale(src: str, obj: str) -> bool:
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    deps = [src, *glob.glob(os.path.join(CSRC, "*.h")), os.path.join(HERE, "..", "include", "hmag.h")]
+    return any(os.path.getmtime(d) > t for d in deps if os.path.exists(d))
+
+
+def _compile(src: str, only_changed: bool = False) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    if only_changed and not _stale(src, obj):
+        return obj
     cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
     p = subprocess.run(cmd, capture_output=True, text=True)
     err = "\n".join(l for l in (p.stderr or "").splitlines() if "not a recognized feature" not in l)
@@ -33,12 +44,14 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int | None = None) -> str:
+def build(jobs: int | None = None, only_changed: bool = False) -> str:
+    """Compile every source (only_changed: skip objects newer than their source and every header)
+    and link libhmag.so."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 4)))
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(lambda s: _compile(s, only_changed), srcs))
     tmp = LIB + ".tmp"
     subprocess.check_call([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp])
     os.replace(tmp, LIB)
@@ -46,4 +59,4 @@ def build(jobs: int | None = None) -> str:
 
 
 if __name__ == "__main__":
-    print(build())
+    print(build(only_changed="--changed" in sys.argv[1:]))
