@@ -231,6 +231,21 @@ hm_status hm_sre_batched(hm_handle h, const void *const *psis, const int *ns, in
 hm_status hm_sre_sampled(hm_handle h, const void *psi, int n, hm_dtype dtype, const uint64_t *rows,
                          int64_t n_rows, double *out, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* hm_sre without any device allocation, for callers that cannot allocate device memory (code
+ * under stream capture, serving loops, harnesses that forbid hipMalloc): same arguments and results
+ * as hm_sre minus the workspace, bitwise equal to hm_sre's on the same handle options.  The per-shift
+ * sums live in a scratch array inside the library, one per GPU, of HM_SRE_NOALLOC_MAX_BYTES (it
+ * holds 2^16 shifts x (HM_MAX_Q + 1) doubles and stays allocated until the process ends).
+ * Covers the workgroup-resident sizes: 1 <= n <= 16 (HM_C64) or 15 (HM_C128); larger n, or handle
+ * options that select the two-pass kernels, return HM_E_SIZE.  HM_OPT_CHECK_NORM returns
+ * HM_E_UNSUPPORTED (its scalars are allocated on first use).  Every call on a GPU uses that GPU's one
+ * scratch array: calls that overlap on one GPU (other streams, other threads, other handles) race
+ * and must be serialised by the caller; calls on one stream are ordered and safe.  Each call
+ * overwrites every slot it reads, so nothing needs clearing between calls. */
+#define HM_SRE_NOALLOC_MAX_BYTES ((size_t)4718592)
+hm_status hm_sre_noalloc(hm_handle h, const void *psi, int n, hm_dtype dtype, const double *q, int n_q,
+                         double *out, hipStream_t stream);
+
 /* ------------------------------------------------------------------------------------------ */
 /* Qutrits: pure-state mana (Eq. mana2, Algorithm 4)                                            */
 /* ------------------------------------------------------------------------------------------ */

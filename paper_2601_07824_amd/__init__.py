@@ -18,7 +18,7 @@ from typing import Sequence
 
 __all__ = [
     "HmError", "lib", "lib_path", "Context", "default_context", "sre", "sre_partial", "sre_finalize",
-    "sre_rows", "sre_row_values", "sre_grad", "sre_grad_batched", "SRE", "SREBatched", "sre_batched", "sre_sampled", "autotune", "tuned_plan", "mana", "mana_partial", "workspace_size",
+    "sre_rows", "sre_row_values", "sre_noalloc", "sre_grad", "sre_grad_batched", "SRE", "SREBatched", "sre_batched", "sre_sampled", "autotune", "tuned_plan", "mana", "mana_partial", "workspace_size",
     "HM_C64", "HM_C128", "profile_enable", "profile_reset", "profile_read", "OP_SRE", "OP_SRE_ROWS", "OP_ROW_VALUES", "OP_SRE_GRAD", "OP_MANA",
     "OP_SRE_SAMPLED", "OP_SRE_GRAD_BATCHED", "EXPORTED_SYMBOLS",
 ]
@@ -61,6 +61,7 @@ _SIGS = {
     "hm_sre_batched_workspace": (_i, [_vp, ctypes.POINTER(_i), _i, _i, _i, ctypes.POINTER(_sz)]),
     "hm_sre_batched": (_i, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_i), _i, _i, _dp, _i, _vp, _vp, _sz, _vp]),
     "hm_sre_sampled": (_i, [_vp, _vp, _i, _i, _vp, _i64, _vp, _vp, _sz, _vp]),
+    "hm_sre_noalloc": (_i, [_vp, _vp, _i, _i, _dp, _i, _vp, _vp]),
     "hm_autotune_workspace": (_i, [_vp, _i, _i, _i64, ctypes.POINTER(_sz)]),
     "hm_autotune": (_i, [_vp, _vp, _i, _i, _i64, _vp, _sz, _vp]),
     "hm_tune_query": (_i, [_vp, _i, _i, ctypes.POINTER(_i64), _dp]),
@@ -248,6 +249,23 @@ def sre(psi, q: Sequence[float] | float = (2.0,), *, ctx: Context | None = None,
     ws = _workspace(workspace_size(OP_SRE, n, dt, nq, 0, ctx), psi.device, stream)
     out = torch.empty(nq + 1, dtype=torch.float64, device=psi.device)
     _check(lib().hm_sre(ctx.h, _ptr(psi), n, dt, qa, nq, _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
+    return out
+
+
+def sre_noalloc(psi, q: Sequence[float] | float = (2.0,), *, out=None, ctx: Context | None = None, stream=None):
+    """hm_sre_noalloc: [M_q..., lost_norm] with no device allocation inside the library (its scratch
+    array is used instead of a workspace).  `out` (float64, n_q + 1 values, on the state's device) may
+    be given so that the call allocates nothing on the Python side either."""
+    torch = _torch()
+    ctx = ctx or default_context()
+    psi, n = _state(psi, 2)
+    qa, nq = _q(q)
+    dt = _dtype_code(psi)
+    if out is None:
+        out = torch.empty(nq + 1, dtype=torch.float64, device=psi.device)
+    elif out.dtype != torch.float64 or out.numel() < nq + 1 or not out.is_contiguous() or out.device != psi.device:
+        raise ValueError("out must be a contiguous float64 tensor of n_q + 1 values on the state's device")
+    _check(lib().hm_sre_noalloc(ctx.h, _ptr(psi), n, dt, qa, nq, _ptr(out), _stream(stream)))
     return out
 
 
