@@ -449,35 +449,46 @@ def sre_grad_batched(states, q: float = 2.0, *, ctx: Context | None = None, stre
 def _make_autograd():
     torch = _torch()
 
+    def _needs_grad(ctx_, q):
+        need = bool(ctx_.needs_input_grad[0])
+        if need and float(q) == 1.0:
+            raise ValueError("the gradient of M_q is built for q != 1 (q = 1 is the Shannon limit); "
+                             "call with a state that does not require grad, or another q")
+        return need
+
     class SRE(torch.autograd.Function):
-        """M_q(psi) as a differentiable scalar; backward runs the fused forward + adjoint kernel."""
+        """M_q(psi) as a differentiable scalar.  When psi requires grad, forward runs the fused
+        forward + adjoint kernel once and keeps dM/dpsi for backward (one library call per step);
+        otherwise it runs the plain forward."""
 
         @staticmethod
         def forward(ctx_, psi, q=2.0):
-            ctx_.save_for_backward(psi)
-            ctx_.q = float(q)
+            if _needs_grad(ctx_, q):
+                out, grad = sre_grad(psi, float(q))
+                ctx_.save_for_backward(grad)
+                return out[0]
             return sre(psi, (float(q),))[0]
 
         @staticmethod
         def backward(ctx_, g):
-            (psi,) = ctx_.saved_tensors
-            _, grad = sre_grad(psi, ctx_.q)
+            (grad,) = ctx_.saved_tensors
             return grad * g.to(grad.real.dtype), None
 
     class SREBatched(torch.autograd.Function):
-        """M_q of each row of a (B, 2^n) batch as a differentiable vector; backward runs the batched
-        fused forward + adjoint."""
+        """M_q of each row of a (B, 2^n) batch as a differentiable vector; with grad required, forward
+        runs the batched fused forward + adjoint once and keeps the gradients for backward."""
 
         @staticmethod
         def forward(ctx_, psis, q=2.0):
-            ctx_.save_for_backward(psis)
-            ctx_.q = float(q)
+            if _needs_grad(ctx_, q):
+                out, grads = sre_grad_batched(psis, float(q))
+                ctx_.save_for_backward(grads)
+                return out[:, 0]
             return sre_batched(list(psis.contiguous().unbind(0)), (float(q),))[:, 0]
 
         @staticmethod
         def backward(ctx_, g):
-            (psis,) = ctx_.saved_tensors
-            _, grads = sre_grad_batched(psis, ctx_.q)
+            (grads,) = ctx_.saved_tensors
             return grads * g.to(grads.real.dtype)[:, None], None
 
     return SRE, SREBatched

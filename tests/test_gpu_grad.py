@@ -259,3 +259,36 @@ def test_grad_fractional_q(orc, hm, c64, n, forced):
     want_out, want_g = orc.sre_grad_direct(w, 1.5) if n <= 7 else orc.sre_grad_fwht(w, 1.5)
     assert rel_l2(g.cpu().numpy().astype(np.complex128), want_g) < (1e-4 if c64 else 1e-9)
     np.testing.assert_allclose(out.cpu().numpy(), want_out, rtol=(1e-5 if c64 else 1e-11), atol=1e-6 if c64 else 1e-12)
+
+
+def test_autograd_step_is_one_fused_call(hm, monkeypatch):
+    """With psi requiring grad, SRE.apply runs hm_sre_grad once in forward and nothing in backward;
+    the value equals the fused call's M_q and the gradient its dM/dpsi (bitwise)."""
+    import paper_2601_07824_amd as mod
+    calls = {"sre": 0, "sre_grad": 0}
+    real_sre, real_grad = mod.sre, mod.sre_grad
+
+    def c_sre(*a, **k):
+        calls["sre"] += 1
+        return real_sre(*a, **k)
+
+    def c_grad(*a, **k):
+        calls["sre_grad"] += 1
+        return real_grad(*a, **k)
+
+    monkeypatch.setattr(mod, "sre", c_sre)
+    monkeypatch.setattr(mod, "sre_grad", c_grad)
+    x, _ = gpu_state(S.gaussian_state(12, seed=6600), True)
+    say("[grad autograd] one fused call per step, n=12 c64")
+    xg = x.clone().requires_grad_(True)
+    m = hm.SRE.apply(xg, 2.0)
+    m.backward()
+    assert calls == {"sre": 0, "sre_grad": 1}, calls
+    out, g = real_grad(x, 2.0)
+    assert m.item() == out[0].item()
+    assert torch.equal(xg.grad, g)
+    calls.update(sre=0, sre_grad=0)
+    with torch.no_grad():
+        m0 = hm.SRE.apply(x, 2.0)
+    assert calls == {"sre": 1, "sre_grad": 0}, calls
+    assert abs(m0.item() - out[0].item()) < 1e-5 * abs(out[0].item())
