@@ -210,9 +210,7 @@ hm_status hm_workspace_size(hm_handle h, hm_op op, int n, hm_dtype dtype, int n_
     }
     case HM_OP_MANA: {
       if (n < 1 || n > 16) return (hm_status)fail(E_SIZE, "mana: n = %d outside [1, 16]", n);
-      uint64_t D = 1;
-      for (int i = 0; i < n; ++i) D *= 3;
-      *bytes = mana_workspace(n, dbl, h->opts.batch, (int)h->opts.streams, D);
+      HM_TRY(mana_workspace(n, dbl, h->opts.batch, (int)h->opts.streams, bytes));
       return HM_OK;
     }
   }
@@ -490,7 +488,9 @@ hm_status hm_mana(hm_handle h, const void *psi, int n, hm_dtype dtype, double *o
   HM_TRY(check_ptr(out, 8, "out"));
   uint64_t D = 1;
   for (int i = 0; i < n; ++i) D *= 3;
-  HM_TRY(check_ws(ws, ws_bytes, mana_workspace(n, dtype == HM_C128, h->opts.batch, (int)h->opts.streams, D)));
+  size_t need = 0;
+  HM_TRY(mana_workspace(n, dtype == HM_C128, h->opts.batch, (int)h->opts.streams, &need));
+  HM_TRY(check_ws(ws, ws_bytes, need));
   HM_TRY(norm_ok(h, psi, 3, n, dtype, stream));
   return (hm_status)mana_launch(n, dtype == HM_C128, h->opts.batch, (int)h->opts.streams, psi, 0, D, nullptr, out, ws, ws_bytes, stream);
 }
@@ -506,7 +506,9 @@ hm_status hm_mana_partial(hm_handle h, const void *psi, int n, hm_dtype dtype, u
   uint64_t D = 1;
   for (int i = 0; i < n; ++i) D *= 3;
   if (a0 > a1 || a1 > D) return (hm_status)fail(E_ARG, "shift range [%llu, %llu) not inside [0, 3^%d]", (unsigned long long)a0, (unsigned long long)a1, n);
-  HM_TRY(check_ws(ws, ws_bytes, mana_workspace(n, dtype == HM_C128, h->opts.batch, (int)h->opts.streams, a1 - a0)));
+  size_t need = 0;
+  HM_TRY(mana_workspace(n, dtype == HM_C128, h->opts.batch, (int)h->opts.streams, &need));
+  HM_TRY(check_ws(ws, ws_bytes, need));
   HM_TRY(norm_ok(h, psi, 3, n, dtype, stream));
   if (a1 == a0) return (hm_status)fill_dev(sums, 3, 0.0, stream);
   return (hm_status)mana_launch(n, dtype == HM_C128, h->opts.batch, (int)h->opts.streams, psi, a0, a1, sums, nullptr, ws, ws_bytes, stream);

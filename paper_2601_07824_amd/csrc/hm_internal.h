@@ -193,6 +193,7 @@ size_t sre_grad2_workspace_f64(const SrePlan &p);
 // streams: two-pass batches alternate over 1 or 2 streams (0 = automatic, HM_OPT_STREAMS).
 int mana_launch(int N, int dbl, int64_t batch, int streams, const void *psi, uint64_t a0, uint64_t a1, double *sums,
                 double *out, void *ws, size_t ws_bytes, hipStream_t stream);
-size_t mana_workspace(int N, int dbl, int64_t batch, int streams, uint64_t n_shifts);
+// Workspace bytes of a mana call (E_SIZE when n has no plan).
+int mana_workspace(int N, int dbl, int64_t batch, int streams, size_t *bytes);
 
 }  // namespace hm

@@ -304,3 +304,16 @@ int main(void) {
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, (r.returncode, r.stdout, r.stderr)
     assert "gfx950" in r.stdout and "HM_E_ARG" in r.stdout
+
+
+def test_mana_workspace_every_size_and_dtype(L, h):
+    """hm_workspace_size(HM_OP_MANA) plans every n in [1, 16] for both dtypes (complex128 two-pass
+    tiles of 3^8 at n = 15, 16) and returns HM_E_SIZE outside that range."""
+    b = ctypes.c_size_t(0)
+    for dt in (0, 1):
+        for n in range(1, 17):
+            assert L.hm_workspace_size(h, 4, n, dt, 1, 0, ctypes.byref(b)) == HM_OK, (n, dt, L.hm_last_error())
+            assert b.value >= 256
+        for n in (0, 17):
+            assert L.hm_workspace_size(h, 4, n, dt, 1, 0, ctypes.byref(b)) == HM_E_SIZE
+

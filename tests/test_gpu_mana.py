@@ -196,3 +196,35 @@ def test_maximum_size_partial(orc, hm):
         got = hm.mana_partial(x, a0, a1).cpu().numpy()
         want = orc.mana_fft_sums(w, a0, a1)
         np.testing.assert_allclose(got, want, rtol=2e-5, atol=1e-6)
+
+
+@pytest.mark.parametrize("n", [13, 14, 15, 16])
+def test_c128_large_sizes_partial(orc, hm, n):
+    """complex128 two-pass tiles up to n = 16 (rows and columns of 3^8 at n = 15, 16): sums over two
+    ragged shift ranges against the oracle (full evaluations there take minutes to hours)."""
+    g = np.random.default_rng(5700 + n)
+    psi = (g.standard_normal(3 ** n) + 1j * g.standard_normal(3 ** n)).astype(np.complex128)
+    psi /= np.linalg.norm(psi)
+    x = torch.from_numpy(psi).to(_dev())
+    for a0, a1 in ((0, 3), (3 ** (n - 1) + 1, 3 ** (n - 1) + 4)):
+        say(f"[mana c128 large] n={n} [{a0},{a1})")
+        got = hm.mana_partial(x, a0, a1).cpu().numpy()
+        want = orc.mana_fft_sums(psi, a0, a1)
+        np.testing.assert_allclose(got, want, rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("c64", [False, True])
+@pytest.mark.parametrize("n", [9, 10, 11, 12, 13])
+def test_row_tiles_ragged_batches(orc, hm, n, c64):
+    """Every two-pass row-tile shape (rows of 3^4..3^7 values, 1 to 27 rows per tile) with launch
+    batches of 5 shifts (3 pairs, the last launch ragged) over an odd shift range, against the
+    oracle's sums over the same range."""
+    psi = S.gaussian_state(n, d=3, seed=5800 + n)
+    x, w = gpu_state(psi, c64)
+    ctx = hm.Context()
+    ctx.batch_shifts(5)
+    a0, a1 = 3 ** n // 2 - 7, 3 ** n // 2 + 6
+    say(f"[mana row tiles] n={n} c64={c64} [{a0},{a1})")
+    got = hm.mana_partial(x, a0, a1, ctx=ctx).cpu().numpy()
+    want = orc.mana_fft_sums(w, a0, a1)
+    np.testing.assert_allclose(got, want, rtol=(1e-10 if not c64 else 2e-6), atol=1e-9)
