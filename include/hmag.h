@@ -231,6 +231,47 @@ hm_status hm_sre_batched(hm_handle h, const void *const *psis, const int *ns, in
 hm_status hm_sre_sampled(hm_handle h, const void *psi, int n, hm_dtype dtype, const uint64_t *rows,
                          int64_t n_rows, double *out, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* Monte Carlo estimate of M_2 by thermodynamic integration (sampling algorithm for the SRE,
+ * Sec. "Monte Carlo sampling algorithm for SRE": Eqs. feP, Boltz, f_expect_beta_reg, Ie, Var_I_eps,
+ * m2error).  L = n_beta inverse temperatures beta_l = l / (L - 1) (L odd: composite Simpson rule),
+ * R = chains_per_beta independent Metropolis chains at each, C = L R chains in all (chain
+ * c = l R + r).  Each chain walks over X-strings a with the energy f(a) = -ln(S'(a) + epsilon),
+ * S(a) = sum_b chi_b(a)^4 evaluated by one Walsh-Hadamard transform per proposal (Eq. feP with the
+ * natural log, which the Boltzmann and integration identities require), proposal a' = a XOR m and
+ * acceptance min(1, exp(-beta_l (f(a') - f(a)))), always at beta = 0.  With exclude_identity = 1
+ * the identity string (a = 0, b = 0) is left out of the sampled energy, S'(0) = S(0) - <I>^4,
+ * and added back exactly.  <f>_beta_l is the mean of the chains' energies after n_therm steps,
+ * I = sum_l w_l <f>_beta_l (Simpson weights) estimates ln Z_0 - ln Z_1 (Eq. f_expect_beta_reg
+ * integrated; the paper's Eq. TI_logZ_reg carries the opposite sign), and
+ *   M2_hat = -log2(e^-I - epsilon + exclude_identity 2^-n),
+ *   dM2 = e^-I / (e^-I - epsilon + ...) sqrt(sum_l w_l^2 var_l) / ln 2,
+ *   var_l = sum_r 2 tau_r sigma_r^2 / ((n_steps - n_therm) R^2), tau_r the integrated
+ *   autocorrelation time of chain r (window: smallest W >= 5 tau(W)).
+ * The randomness is the caller's (device arrays, e.g. drawn from a seeded generator):
+ *   a_init: C initial X-strings; moves: n_steps x C XOR masks (step-major); uniforms: n_steps x C
+ *   numbers in [0, 1) for the acceptance tests.  Bits at or above n are ignored.
+ * Outputs (device): trace: n_steps x C doubles, the energy of each chain after each step;
+ *   out: 4 + 5 L doubles = {M2_hat, dM2, I, S2_hat = 2^n (e^-I - epsilon + ...)}, then per beta_l:
+ *   {<f>_l, variance of <f>_l, sigma_f^2 (mean over its chains), tau_int (mean), acceptance rate}.
+ * A zero row sum with epsilon = 0 gives f = +inf (never entered at beta > 0; the beta = 0 chains
+ * then make the result infinite or NaN): use epsilon > 0 for states with vanishing sectors.
+ * Per step: one row launch over the C proposals (hm_sre_rows' kernels) and one small kernel; n_steps
+ * steps are enqueued without host synchronisation.  1 <= n <= 26 (HM_C64) / 25 (HM_C128).
+ * Workspace: hm_sre_mc_workspace (2^n doubles for S'(0) when exclude_identity, plus the row
+ * kernels' workspace and O(C) chain state). */
+typedef struct {
+  int n_beta;           /* L: odd, 3 <= L <= 1025                                   */
+  int chains_per_beta;  /* R >= 1, L R <= 2^20                                      */
+  int64_t n_steps;      /* Metropolis steps per chain, >= 2                         */
+  int64_t n_therm;      /* leading steps left out of the averages, <= n_steps - 2   */
+  double epsilon;       /* regulariser of Eq. feP, >= 0                             */
+  int exclude_identity; /* 0 or 1                                                   */
+} hm_mc_params;
+hm_status hm_sre_mc_workspace(hm_handle h, int n, hm_dtype dtype, const hm_mc_params *params, size_t *bytes);
+hm_status hm_sre_mc(hm_handle h, const void *psi, int n, hm_dtype dtype, const hm_mc_params *params,
+                    const uint64_t *a_init, const uint64_t *moves, const double *uniforms, double *out,
+                    double *trace, void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* hm_sre without any device allocation, for callers that cannot allocate device memory (code
  * under stream capture, serving loops, harnesses that forbid hipMalloc): same arguments and results
  * as hm_sre minus the workspace, bitwise equal to hm_sre's on the same handle options.  The per-shift

@@ -18,7 +18,7 @@ from typing import Sequence
 
 __all__ = [
     "HmError", "lib", "lib_path", "Context", "default_context", "sre", "sre_partial", "sre_finalize",
-    "sre_rows", "sre_row_values", "sre_noalloc", "sre_grad", "sre_grad_batched", "SRE", "SREBatched", "sre_batched", "sre_sampled", "autotune", "tuned_plan", "mana", "mana_partial", "workspace_size",
+    "sre_rows", "sre_row_values", "sre_noalloc", "sre_mc", "McParams", "mc_random_inputs", "sre_grad", "sre_grad_batched", "SRE", "SREBatched", "sre_batched", "sre_sampled", "autotune", "tuned_plan", "mana", "mana_partial", "workspace_size",
     "HM_C64", "HM_C128", "profile_enable", "profile_reset", "profile_read", "OP_SRE", "OP_SRE_ROWS", "OP_ROW_VALUES", "OP_SRE_GRAD", "OP_MANA",
     "OP_SRE_SAMPLED", "OP_SRE_GRAD_BATCHED", "EXPORTED_SYMBOLS",
 ]
@@ -62,6 +62,8 @@ _SIGS = {
     "hm_sre_batched": (_i, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_i), _i, _i, _dp, _i, _vp, _vp, _sz, _vp]),
     "hm_sre_sampled": (_i, [_vp, _vp, _i, _i, _vp, _i64, _vp, _vp, _sz, _vp]),
     "hm_sre_noalloc": (_i, [_vp, _vp, _i, _i, _dp, _i, _vp, _vp]),
+    "hm_sre_mc_workspace": (_i, [_vp, _i, _i, _vp, ctypes.POINTER(_sz)]),
+    "hm_sre_mc": (_i, [_vp, _vp, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "hm_autotune_workspace": (_i, [_vp, _i, _i, _i64, ctypes.POINTER(_sz)]),
     "hm_autotune": (_i, [_vp, _vp, _i, _i, _i64, _vp, _sz, _vp]),
     "hm_tune_query": (_i, [_vp, _i, _i, ctypes.POINTER(_i64), _dp]),
@@ -382,6 +384,58 @@ def sre_sampled(psi, n_rows: int = 4096, seed: int = 0, rows=None, *, ctx: Conte
     _check(lib().hm_sre_sampled(ctx.h, _ptr(psi), n, dt, _ptr(rows), rows.numel(), _ptr(out), _ptr(ws), ws.numel(),
                                 _stream(stream)))
     return out
+
+
+class McParams(ctypes.Structure):
+    """hm_mc_params (include/hmag.h)."""
+    _fields_ = [("n_beta", _i), ("chains_per_beta", _i), ("n_steps", _i64), ("n_therm", _i64),
+                ("epsilon", ctypes.c_double), ("exclude_identity", _i)]
+
+
+def mc_random_inputs(n: int, n_beta: int, chains_per_beta: int, n_steps: int, seed: int):
+    """The chains' randomness drawn with numpy's PCG64 (seed): initial X-strings uniform in [1, 2^n),
+    single-bit-flip XOR masks and acceptance uniforms, each (n_steps, C) with C = n_beta chains_per_beta."""
+    import numpy as np
+    C = n_beta * chains_per_beta
+    g = np.random.default_rng(seed)
+    a_init = g.integers(1, 2 ** n, size=C, dtype=np.uint64)
+    moves = np.uint64(1) << g.integers(0, n, size=(n_steps, C)).astype(np.uint64)
+    uniforms = g.random((n_steps, C))
+    return a_init, moves, uniforms
+
+
+def sre_mc(psi, n_beta: int = 17, chains_per_beta: int = 1, n_steps: int = 1000, n_therm: int = 100,
+           epsilon: float = 0.0, exclude_identity: bool = True, seed: int = 0, inputs=None, *,
+           ctx: Context | None = None, stream=None):
+    """Monte Carlo M_2 by thermodynamic integration (hm_sre_mc).  inputs = (a_init, moves, uniforms)
+    as numpy arrays, else drawn by mc_random_inputs(seed).  Returns (out, trace): out = [M2_hat, dM2,
+    I, S2_hat, then per beta point <f>, var, sigma^2, tau_int, acceptance] (float64 tensor), trace =
+    (n_steps, C) energies."""
+    import numpy as np
+    torch = _torch()
+    ctx = ctx or default_context()
+    psi, n = _state(psi, 2)
+    dt = _dtype_code(psi)
+    C = n_beta * chains_per_beta
+    if inputs is None:
+        inputs = mc_random_inputs(n, n_beta, chains_per_beta, n_steps, seed)
+    a_init, moves, uniforms = (np.ascontiguousarray(v) for v in inputs)
+    if a_init.shape != (C,) or moves.shape != (n_steps, C) or uniforms.shape != (n_steps, C):
+        raise ValueError("inputs must have shapes (C,), (n_steps, C), (n_steps, C)")
+    dev = psi.device
+    a_t = torch.from_numpy(a_init.astype(np.uint64).view(np.int64)).to(dev)
+    m_t = torch.from_numpy(moves.astype(np.uint64).view(np.int64)).to(dev)
+    u_t = torch.from_numpy(uniforms.astype(np.float64)).to(dev)
+    prm = McParams(n_beta, chains_per_beta, n_steps, n_therm, float(epsilon), int(bool(exclude_identity)))
+    b = _sz(0)
+    _check(lib().hm_sre_mc_workspace(ctx.h, n, dt, ctypes.byref(prm), ctypes.byref(b)))
+    ws = _workspace(b.value, dev, stream)
+    out = torch.empty(4 + 5 * n_beta, dtype=torch.float64, device=dev)
+    trace = torch.empty((n_steps, C), dtype=torch.float64, device=dev)
+    _check(lib().hm_sre_mc(ctx.h, _ptr(psi), n, dt, ctypes.byref(prm), _ptr(a_t), _ptr(m_t), _ptr(u_t), _ptr(out),
+                           _ptr(trace), _ptr(ws), ws.numel(), _stream(stream)))
+    out._hm_keepalive = (a_t, m_t, u_t, ws)
+    return out, trace
 
 
 def sre_row_values(psi, a: int, *, ctx: Context | None = None, stream=None):

@@ -81,6 +81,12 @@ static int fill_dev(double *p, int64_t n, double v, hipStream_t st) {
   return hipPeekAtLastError() == hipSuccess ? OK : fail(E_HIP, "fill launch: %s", hipGetErrorString(hipGetLastError()));
 }
 
+// Monte Carlo by thermodynamic integration (hm_mc.hip).
+int mc_check(int n, const hm_mc_params *prm);
+int mc_workspace(const SrePlan &p, const hm_mc_params *prm, size_t *bytes);
+int mc_run(const SrePlan &p, const void *psi, const hm_mc_params *prm, const uint64_t *a_init, const uint64_t *moves,
+           const double *uniforms, double *out, double *trace, void *ws, hipStream_t st);
+
 }  // namespace hm
 
 using namespace hm;
@@ -434,6 +440,38 @@ hm_status hm_sre_sampled(hm_handle h, const void *psi, int n, hm_dtype dtype, co
   HM_TRY(sre_run(p, psi, qa, 0, nullptr, 1, s0, nullptr, nullptr, (char *)ws + rs_bytes, stream));
   HM_TRY(sre_run(p, psi, qa, 0, rows, n_rows, rs, nullptr, nullptr, (char *)ws + rs_bytes, stream));
   return (hm_status)sre_sampled_stats(rs, rows, n_rows, 2, s0, n, out, stream);
+}
+
+hm_status hm_sre_mc_workspace(hm_handle h, int n, hm_dtype dtype, const hm_mc_params *params, size_t *bytes) {
+  g_err[0] = 0;
+  if (!h || !bytes) return (hm_status)fail(E_ARG, "h or bytes is NULL");
+  HM_TRY(check_dtype(dtype));
+  HM_TRY(mc_check(n, params));
+  SrePlan p;
+  HM_TRY(sre_plan(n, dtype == HM_C128, plan_opts(h, n, dtype == HM_C128), &p));
+  return (hm_status)mc_workspace(p, params, bytes);
+}
+
+hm_status hm_sre_mc(hm_handle h, const void *psi, int n, hm_dtype dtype, const hm_mc_params *params,
+                    const uint64_t *a_init, const uint64_t *moves, const double *uniforms, double *out, double *trace,
+                    void *ws, size_t ws_bytes, hipStream_t stream) {
+  g_err[0] = 0;
+  if (!h) return (hm_status)fail(E_ARG, "h is NULL");
+  HM_TRY(check_dtype(dtype));
+  HM_TRY(check_ptr(psi, psi_align(dtype), "psi"));
+  HM_TRY(mc_check(n, params));
+  HM_TRY(check_ptr(a_init, 8, "a_init"));
+  HM_TRY(check_ptr(moves, 8, "moves"));
+  HM_TRY(check_ptr(uniforms, 8, "uniforms"));
+  HM_TRY(check_ptr(out, 8, "out"));
+  HM_TRY(check_ptr(trace, 8, "trace"));
+  SrePlan p;
+  HM_TRY(sre_plan(n, dtype == HM_C128, plan_opts(h, n, dtype == HM_C128), &p));
+  size_t need = 0;
+  HM_TRY(mc_workspace(p, params, &need));
+  HM_TRY(check_ws(ws, ws_bytes, need));
+  HM_TRY(norm_ok(h, psi, 2, n, dtype, stream));
+  return (hm_status)mc_run(p, psi, params, a_init, moves, uniforms, out, trace, ws, stream);
 }
 
 hm_status hm_autotune_workspace(hm_handle h, int n, hm_dtype dtype, int64_t sample_shifts, size_t *bytes) {

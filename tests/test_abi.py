@@ -317,3 +317,21 @@ def test_mana_workspace_every_size_and_dtype(L, h):
         for n in (0, 17):
             assert L.hm_workspace_size(h, 4, n, dt, 1, 0, ctypes.byref(b)) == HM_E_SIZE
 
+
+
+def test_mc_argument_errors(L, h):
+    prm = hm.McParams(5, 2, 100, 10, 0.0, 1)
+    b = ctypes.c_size_t(0)
+    assert L.hm_sre_mc_workspace(h, 10, 0, ctypes.byref(prm), ctypes.byref(b)) == HM_OK
+    assert b.value > 0
+    good = P(0x100000)
+    args = lambda p: (h, good, 10, 0, ctypes.byref(p), good, good, good, good, good, good, 1 << 40, None)
+    for bad in (hm.McParams(4, 2, 100, 10, 0.0, 1), hm.McParams(1, 2, 100, 10, 0.0, 1),
+                hm.McParams(5, 0, 100, 10, 0.0, 1), hm.McParams(5, 2, 1, 0, 0.0, 1),
+                hm.McParams(5, 2, 100, 99, 0.0, 1), hm.McParams(5, 2, 100, 10, -1.0, 1),
+                hm.McParams(5, 2, 100, 10, float("nan"), 1), hm.McParams(5, 2, 100, 10, 0.0, 2)):
+        assert L.hm_sre_mc(*args(bad)) == HM_E_ARG, (bad.n_beta, bad.chains_per_beta, bad.n_steps, bad.n_therm)
+    assert L.hm_sre_mc(h, good, 10, 0, None, good, good, good, good, good, good, 1 << 40, None) == HM_E_ARG
+    assert L.hm_sre_mc(h, good, 10, 0, ctypes.byref(prm), None, good, good, good, good, good, 1 << 40, None) == HM_E_ARG
+    assert L.hm_sre_mc(h, good, 27, 0, ctypes.byref(prm), good, good, good, good, good, good, 1 << 40, None) == HM_E_SIZE
+    assert L.hm_sre_mc(h, good, 10, 0, ctypes.byref(prm), good, good, good, good, good, good, 16, None) == HM_E_WORKSPACE
