@@ -98,6 +98,10 @@ const char *hm_version(void);
  *     and lost_norm reports the deviation.  The check's two scalars (one device, one pinned host
  *     double per device) are allocated by the library on first use and kept until the process
  *     ends.
+ *   HM_OPT_BATCH_LAUNCH: how hm_sre_batched runs its workgroup-resident states: 1 (default) = one
+ *     persistent launch for all of them, as many workgroups as fit the device taking work units from
+ *     a device counter; 2 = one launch per size class of up to 64 states, each with the kernel
+ *     specialised for that size.
  * A combination outside the built kernels makes the SRE calls return HM_E_UNSUPPORTED. */
 typedef enum {
   HM_OPT_FORCE_PATH = 1,
@@ -108,7 +112,8 @@ typedef enum {
   HM_OPT_PIPELINE = 6,
   HM_OPT_LDS_SPLIT = 7,
   HM_OPT_STREAMS = 8,
-  HM_OPT_CHECK_NORM = 9
+  HM_OPT_CHECK_NORM = 9,
+  HM_OPT_BATCH_LAUNCH = 10
 } hm_option;
 hm_status hm_set_option(hm_handle h, hm_option opt, int64_t value);
 
@@ -205,13 +210,21 @@ hm_status hm_sre_grad_batched(hm_handle h, const void *const *psis, int n, int b
                               double q, double *out, void *const *grads, void *ws, size_t ws_bytes,
                               hipStream_t stream);
 
-/* Many states, each of its own qubit count, in one call (all of one dtype and one q list).
+/* Many states, each of its own qubit count, in one call (all of one dtype and one q list): the
+ * batched form of Algorithm 2 (every X-shift of every state is an independent transform, the
+ * paper's chunking of the X-string loop).
  * psis: HOST array of `batch` DEVICE pointers (one state each); ns: HOST array of their n.
  * out: device, batch * (n_q + 1) doubles; out[s*(n_q+1) + i] = M_{q_i}(psi_s), out[s*(n_q+1) + n_q]
- * = lost_norm of state s (as hm_sre).  States of equal n that fit the workgroup-resident kernels
- * (n <= 16 for HM_C64, n <= 15 for HM_C128) are evaluated together, up to 64 per launch (the state
- * pointers travel in the kernel arguments, no host-to-device copy); larger states run one after
- * another through the two-pass kernels.  Workspace: hm_sre_batched_workspace. */
+ * = lost_norm of state s (as hm_sre).  The states whose folded vector fits one workgroup tile
+ * (6 <= n <= 16 for HM_C64, 5 <= n <= 15 for HM_C128) run in ONE persistent launch: their work
+ * units (tiles of the workgroup-resident row pass: one shift at the largest n, several whole shifts
+ * of smaller states) are numbered largest state first and taken from a device counter by a grid of
+ * as many workgroups as fit the device; the state table reaches the device through kernel arguments
+ * (no host-to-device copy).  One workgroup per state then sums its per-shift sums in a fixed order,
+ * so results are deterministic and equal hm_sre's up to the order of the FP64 sums and the FP32
+ * tile shape.  Smaller states run by size class (up to 64 per launch) and two-pass sizes one after
+ * another, after the persistent launch, on the same workspace.  HM_OPT_BATCH_LAUNCH = 2 runs every
+ * resident size class in a launch of its own instead.  Workspace: hm_sre_batched_workspace. */
 hm_status hm_sre_batched_workspace(hm_handle h, const int *ns, int batch, hm_dtype dtype, int n_q,
                                    size_t *bytes);
 hm_status hm_sre_batched(hm_handle h, const void *const *psis, const int *ns, int batch, hm_dtype dtype,

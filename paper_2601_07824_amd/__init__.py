@@ -31,6 +31,7 @@ OP_SRE, OP_SRE_ROWS, OP_ROW_VALUES, OP_SRE_GRAD, OP_MANA, OP_SRE_SAMPLED, OP_SRE
 OPT_FORCE_PATH, OPT_BATCH_SHIFTS, OPT_ROW_RB, OPT_COL_RB, OPT_ROW_BITS, OPT_PIPELINE, OPT_LDS_SPLIT, OPT_STREAMS = \
     1, 2, 3, 4, 5, 6, 7, 8
 OPT_CHECK_NORM = 9
+OPT_BATCH_LAUNCH = 10
 
 _vp = ctypes.c_void_p
 _i = ctypes.c_int

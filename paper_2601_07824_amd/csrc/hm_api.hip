@@ -165,6 +165,10 @@ hm_status hm_set_option(hm_handle h, hm_option opt, int64_t value) {
       if (value < 0 || value > 2) return (hm_status)fail(E_ARG, "HM_OPT_STREAMS %lld not in {0,1,2}", (long long)value);
       h->opts.streams = (int)value;
       return HM_OK;
+    case HM_OPT_BATCH_LAUNCH:
+      if (value < 0 || value > 2) return (hm_status)fail(E_ARG, "HM_OPT_BATCH_LAUNCH %lld not in {0,1,2}", (long long)value);
+      h->opts.batch_launch = (int)value;
+      return HM_OK;
     case HM_OPT_CHECK_NORM:
       if (value < 0 || value > 1) return (hm_status)fail(E_ARG, "HM_OPT_CHECK_NORM %lld not in {0,1}", (long long)value);
       h->check_norm = (int)value;
@@ -343,7 +347,26 @@ hm_status hm_sre_grad_batched(hm_handle h, const void *const *psis, int n, int b
   return (hm_status)sre_grad_batched_launch(o, n, dtype == HM_C128, psis, batch, q, out, grads, ws, ws_bytes, stream);
 }
 
-// Workspace of a batched call: the largest need over its size classes.
+// Default launch form of the batched forward (HM_OPT_BATCH_LAUNCH).
+static constexpr int BATCH_LAUNCH_DEFAULT = 1;
+
+// Batched calls: states of workgroup-resident size (path 1 under the handle's options, at least
+// 2^RB folded values) go to one persistent launch; the rest (tiny states, two-pass sizes) run by
+// size class / one after another on the same workspace after it.
+static void batched_split(hm_handle h, const int *ns, int batch, int dbl, std::vector<int> *pers,
+                          std::vector<int> *rest) {
+  const int mode = h->opts.batch_launch ? h->opts.batch_launch : BATCH_LAUNCH_DEFAULT;
+  for (int i = 0; i < batch; ++i) {
+    if (mode == 2) {
+      rest->push_back(i);
+      continue;
+    }
+    SrePlan p;
+    const bool res = sre_plan(ns[i], dbl, plan_opts(h, ns[i], dbl), &p) == OK && p.path == 1;
+    (res && batch_resident_ok(ns[i], dbl) ? pers : rest)->push_back(i);
+  }
+}
+
 static int batched_ws(hm_handle h, const int *ns, int batch, int dbl, int n_q, size_t *bytes) {
   if (!ns || batch < 1) return fail(E_ARG, "batched: ns is NULL or batch = %d < 1", batch);
   size_t need = 256;
@@ -351,10 +374,17 @@ static int batched_ws(hm_handle h, const int *ns, int batch, int dbl, int n_q, s
     SrePlan p;
     int st = sre_plan(ns[i], dbl, plan_opts(h, ns[i], dbl), &p);
     if (st) return st;
+  }
+  std::vector<int> pers, rest;
+  batched_split(h, ns, batch, dbl, &pers, &rest);
+  if (!pers.empty()) need = batch_persistent_workspace(ns, pers.data(), (int)pers.size(), n_q, dbl);
+  for (int i : rest) {
+    SrePlan p;
+    sre_plan(ns[i], dbl, plan_opts(h, ns[i], dbl), &p);
     size_t b;
     if (p.path == 1) {
       int cnt = 0;
-      for (int j = 0; j < batch; ++j) cnt += ns[j] == ns[i];
+      for (int j : rest) cnt += ns[j] == ns[i];
       b = sre_states_workspace(p, n_q, cnt < HM_BATCH_PTRS ? cnt : HM_BATCH_PTRS);
     } else {
       b = sre_workspace(p, n_q, (int64_t)1 << ns[i]);
@@ -388,9 +418,12 @@ hm_status hm_sre_batched(hm_handle h, const void *const *psis, const int *ns, in
   for (int i = 0; i < batch; ++i) HM_TRY(check_ptr(psis[i], psi_align(dtype), "psis[i]"));
   HM_TRY(check_ws(ws, ws_bytes, need));
   for (int i = 0; i < batch; ++i) HM_TRY(norm_ok(h, psis[i], 2, ns[i], dtype, stream));
-  // size classes in order of first appearance; resident classes go up to HM_BATCH_PTRS per launch
+  std::vector<int> pers, rest;
+  batched_split(h, ns, batch, dbl, &pers, &rest);
+  HM_TRY(batch_persistent_run(dbl, psis, ns, pers.data(), (int)pers.size(), qa, out, ws, stream));
+  // the rest: resident size classes up to HM_BATCH_PTRS states per launch, two-pass states one by one
   std::vector<char> done(batch, 0);
-  for (int i = 0; i < batch; ++i) {
+  for (int i : rest) {
     if (done[i]) continue;
     SrePlan p;
     HM_TRY(sre_plan(ns[i], dbl, plan_opts(h, ns[i], dbl), &p));
@@ -402,7 +435,7 @@ hm_status hm_sre_batched(hm_handle h, const void *const *psis, const int *ns, in
     }
     std::vector<const void *> ptrs;
     std::vector<double *> outs;
-    for (int j = i; j < batch; ++j) {
+    for (int j : rest) {
       if (done[j] || ns[j] != ns[i]) continue;
       done[j] = 1;
       ptrs.push_back(psis[j]);

@@ -96,6 +96,7 @@ struct PlanOpts {
   int pipeline = 0;  // 0 automatic, 1 off, 2 on
   int lds_split = 0; // 0 automatic, 1 off, 2 on
   int streams = 0;   // 0 automatic, 1 or 2
+  int batch_launch = 0;  // hm_sre_batched: 0 automatic, 1 one persistent launch, 2 one launch per size class
 };
 
 // Plan options chosen by the autotuner for one (qubit count, dtype).
@@ -145,6 +146,13 @@ int sre_reduce_shifts(const double *shift_sums, int64_t n_slots, const QArgs &qa
 int sre_run_states(const SrePlan &p, const void *const *psis, int n_states, const QArgs &qa, double *const *outs,
                    void *ws, hipStream_t stream);
 size_t sre_states_workspace(const SrePlan &p, int nq, int n_states);
+// Many states of uneven size in one persistent launch (hm_batch.hip): states whose folded vector
+// fits one workgroup tile (batch_resident_ok), all shifts of all of them.  out[s (nq+1) ...] for
+// each selected s.
+bool batch_resident_ok(int N, int dbl);
+size_t batch_persistent_workspace(const int *ns, const int *sel, int cnt, int nq, int dbl);
+int batch_persistent_run(int dbl, const void *const *psis, const int *ns, const int *sel, int cnt, const QArgs &qa,
+                         double *out, void *ws, hipStream_t stream);
 // Monte Carlo M_2 from the row sums of sampled rows (rows equal to 0 skipped) and the exact row
 // sums of a = 0: out = {M2_hat, standard error, S_hat, std of the sampled S(a)}.
 int sre_sampled_stats(const double *row_sums, const uint64_t *rows, int64_t n_rows, int nacc, const double *s0_sums,

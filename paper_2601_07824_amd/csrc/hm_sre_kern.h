@@ -65,10 +65,33 @@ struct RowShape {
   static constexpr size_t LDS_BYTES = (size_t)LDS_N * sizeof(Elem);
 };
 
+// Arguments of one state's workgroup-resident tiles inside a persistent launch: the fields of
+// RowPassArgs that a single-state, all-shifts, reducing row pass reads (no pointer table).
+struct StateTileArgs {
+  const void *psi;
+  int nf;
+  static constexpr int nh = 0;
+  int64_t n_slots;
+  static constexpr uint64_t a0 = 0;
+  static constexpr const uint64_t *rows = nullptr;
+  static constexpr void *exch = nullptr;
+  double *shift_sums;
+  int nacc;
+  int64_t n_tiles;
+  const QArgs &qa;  // the launch's Renyi indices (kernel argument), not copied
+  static constexpr int n_states = 0;
+  static constexpr int state_bits = 0;
+  static constexpr const void *psis[1] = {nullptr};
+  __device__ StateTileArgs(const void *psi_, int nf_, double *ss, int nacc_, int64_t n_tiles_, const QArgs &qa_)
+      : psi(psi_), nf(nf_), n_slots((int64_t)1 << (nf_ + 1)), shift_sums(ss), nacc(nacc_), n_tiles(n_tiles_),
+        qa(qa_) {}
+};
+
 // Row tiles t0, t0 + tstep, ... < A.n_tiles.
-template <typename T, int NT, int RB, int NL, bool WRITE, int QM, bool SPLIT>
-__device__ __forceinline__ void rowpass_tiles(const RowPassArgs &A, int64_t t0, int64_t tstep,
-                                              typename RowShape<T, NT, RB, NL, SPLIT>::Elem *lds, double *red) {
+template <typename T, int NT, int RB, int NL, bool WRITE, int QM, bool SPLIT, typename Args = RowPassArgs>
+__device__ __forceinline__ void rowpass_tiles(const Args &A, int64_t t0, int64_t tstep,
+                                              typename RowShape<T, NT, RB, NL, SPLIT>::Elem *lds, double *red,
+                                              uint32_t tau = threadIdx.x) {
   constexpr int R = 1 << RB;
   constexpr int LT = ilog2c(NT);
   constexpr int TB = LT + RB;
@@ -81,7 +104,6 @@ __device__ __forceinline__ void rowpass_tiles(const RowPassArgs &A, int64_t t0, 
   constexpr bool WAVE_UNIFORM = SEG >= 64;
 
   const vec2<T> *__restrict__ psi = (const vec2<T> *)A.psi;
-  const uint32_t tau = threadIdx.x;
   const uint32_t tlo = tau & (SEG - 1);
   const uint32_t g = tau >> S0;
   const uint32_t half = 1u << A.nf;
@@ -96,7 +118,7 @@ __device__ __forceinline__ void rowpass_tiles(const RowPassArgs &A, int64_t t0, 
     const vec2<T> *__restrict__ ps = psi;
     if (active) {
       if (A.n_states > 0) {
-        ps = (const vec2<T> *)A.psis[slot >> A.state_bits];
+        ps = (const vec2<T> *)A.psis[A.n_states > 0 ? slot >> A.state_bits : 0];
         a = (uint64_t)slot & ((1ull << A.state_bits) - 1ull);
       } else {
         a = A.rows ? A.rows[slot] : A.a0 + (uint64_t)slot;

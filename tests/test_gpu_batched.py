@@ -81,6 +81,37 @@ def test_batched_more_than_one_launch(orc, hm):
     assert abs(got[0, 0]) < 1e-10 and abs(got[1, 0] - k * math.log2(4 / 3)) < 1e-9, got
 
 
+def test_batched_1024_states_n10_to_16(orc, hm):
+    """The batched benchmark workload: 1024 complex64 states with N uniform in [10, 16] (seed 5005),
+    one persistent launch.  Every state against its own single call, 24 sampled states against the
+    FP64 oracle."""
+    rng = np.random.default_rng(5005)
+    ns = rng.integers(10, 17, size=1024)
+    psis = [S.gaussian_state(int(n), seed=5000 + i) for i, n in enumerate(ns)]
+    xs, ws = zip(*[gpu_state(p, True) for p in psis])
+    say("[batched 1024] one call")
+    got = hm.sre_batched(list(xs), (2.0,)).cpu().numpy()
+    single = np.stack([hm.sre(x, (2.0,)).cpu().numpy() for x in xs])
+    np.testing.assert_allclose(got[:, 0], single[:, 0], rtol=2e-6, atol=0)
+    for i in np.random.default_rng(5006).choice(1024, 24, replace=False):
+        want = orc.sre_fwht(ws[i], (2.0,))
+        assert abs(got[i, 0] - want[0]) <= 1e-5 * abs(want[0]), (i, ns[i], got[i], want)
+
+
+@pytest.mark.parametrize("c64", [False, True])
+def test_persistent_launch_equals_per_size_launches(hm, c64):
+    """HM_OPT_BATCH_LAUNCH: the one persistent launch (default) and one launch per size class give
+    the same M_2 up to FP64 summation order and the FP32 tile shape."""
+    ns = [15, 6, 11, 9, 13, 6, 15, 7, 12, 10] if c64 else [14, 5, 11, 9, 12, 5, 14, 7, 10]
+    xs = [gpu_state(S.gaussian_state(n, seed=7300 + i), c64)[0] for i, n in enumerate(ns)]
+    per = hm.Context()
+    per.set_option(hm.OPT_BATCH_LAUNCH, 2)
+    say(f"[batched launch forms] c64={c64}")
+    a = hm.sre_batched(xs, (1.0, 2.0)).cpu().numpy()
+    b = hm.sre_batched(xs, (1.0, 2.0), ctx=per).cpu().numpy()
+    np.testing.assert_allclose(a[:, :2], b[:, :2], rtol=(2e-6 if c64 else 1e-12), atol=0)
+
+
 def test_batched_deterministic(hm):
     xs = [gpu_state(S.gaussian_state(n, seed=7200 + n), True)[0] for n in (7, 11, 11, 15)]
     say("[batched determinism]")
