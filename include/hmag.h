@@ -129,12 +129,31 @@ hm_status hm_set_option(hm_handle h, hm_option opt, int64_t value);
 hm_status hm_autotune_workspace(hm_handle h, int n, hm_dtype dtype, int64_t sample_shifts, size_t *bytes);
 hm_status hm_autotune(hm_handle h, const void *psi, int n, hm_dtype dtype, int64_t sample_shifts, void *ws,
                       size_t ws_bytes, hipStream_t stream);
+/* Autotuners of the other plans; each times its candidates on the caller's data (a warm-up and one
+ * timed run each, hipEvents on `stream`, blocking until done), keeps the fastest in the handle and
+ * is used from then on for options left automatic.  Results of the timed runs are discarded.
+ *   hm_autotune_mana: exchange of 128 / 192 / 256 MiB per two-pass launch pair on one or two
+ *     streams, over the first sample_shifts shifts (4096 if <= 0); HM_OPT_BATCH_SHIFTS and
+ *     HM_OPT_STREAMS set on the handle are kept.
+ *   hm_autotune_grad: workgroup-resident or two-pass gradient kernels (where both exist for n), one
+ *     full fused forward + adjoint each; out and grad as hm_sre_grad.
+ *   hm_autotune_batched: hm_sre_batched's launch form (HM_OPT_BATCH_LAUNCH 1 or 2) on the given
+ *     batch, M_2 only; out as hm_sre_batched with n_q = 1; workspace: the larger of the two forms'
+ *     hm_sre_batched_workspace.  HM_E_ARG if HM_OPT_BATCH_LAUNCH is set on the handle. */
+hm_status hm_autotune_mana_workspace(hm_handle h, int n, hm_dtype dtype, size_t *bytes);
+hm_status hm_autotune_mana(hm_handle h, const void *psi, int n, hm_dtype dtype, int64_t sample_shifts, void *ws,
+                           size_t ws_bytes, hipStream_t stream);
+hm_status hm_autotune_grad_workspace(hm_handle h, int n, hm_dtype dtype, size_t *bytes);
+hm_status hm_autotune_grad(hm_handle h, const void *psi, int n, hm_dtype dtype, double q, double *out, void *grad,
+                           void *ws, size_t ws_bytes, hipStream_t stream);
+hm_status hm_autotune_batched(hm_handle h, const void *const *psis, const int *ns, int batch, hm_dtype dtype,
+                              double *out, void *ws, size_t ws_bytes, hipStream_t stream);
 /* The stored plan for (n, dtype): opts[0..7] = {HM_OPT_FORCE_PATH, HM_OPT_BATCH_SHIFTS,
  * HM_OPT_ROW_RB, HM_OPT_COL_RB, HM_OPT_ROW_BITS, HM_OPT_PIPELINE, HM_OPT_LDS_SPLIT, HM_OPT_STREAMS}
  * values (host array of 8), and its measured milliseconds per X-shift.  HM_E_ARG if none is
  * stored. */
 hm_status hm_tune_query(hm_handle h, int n, hm_dtype dtype, int64_t *opts, double *ms_per_shift);
-/* Forgets every stored plan of the handle. */
+/* Forgets every stored plan of the handle (SRE, mana, gradient and batched). */
 hm_status hm_tune_clear(hm_handle h);
 
 /* ------------------------------------------------------------------------------------------ */

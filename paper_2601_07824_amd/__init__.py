@@ -18,7 +18,7 @@ from typing import Sequence
 
 __all__ = [
     "HmError", "lib", "lib_path", "Context", "default_context", "sre", "sre_partial", "sre_finalize",
-    "sre_rows", "sre_row_values", "sre_noalloc", "sre_mc", "McParams", "mc_random_inputs", "sre_grad", "sre_grad_batched", "SRE", "SREBatched", "sre_batched", "sre_sampled", "autotune", "tuned_plan", "mana", "mana_partial", "workspace_size",
+    "sre_rows", "sre_row_values", "sre_noalloc", "sre_mc", "McParams", "mc_random_inputs", "sre_grad", "sre_grad_batched", "SRE", "SREBatched", "sre_batched", "sre_sampled", "autotune", "autotune_mana", "autotune_grad", "autotune_batched", "tuned_plan", "mana", "mana_partial", "workspace_size",
     "HM_C64", "HM_C128", "profile_enable", "profile_reset", "profile_read", "OP_SRE", "OP_SRE_ROWS", "OP_ROW_VALUES", "OP_SRE_GRAD", "OP_MANA",
     "OP_SRE_SAMPLED", "OP_SRE_GRAD_BATCHED", "EXPORTED_SYMBOLS",
 ]
@@ -68,6 +68,11 @@ _SIGS = {
     "hm_autotune_workspace": (_i, [_vp, _i, _i, _i64, ctypes.POINTER(_sz)]),
     "hm_autotune": (_i, [_vp, _vp, _i, _i, _i64, _vp, _sz, _vp]),
     "hm_tune_query": (_i, [_vp, _i, _i, ctypes.POINTER(_i64), _dp]),
+    "hm_autotune_mana_workspace": (_i, [_vp, _i, _i, ctypes.POINTER(_sz)]),
+    "hm_autotune_mana": (_i, [_vp, _vp, _i, _i, _i64, _vp, _sz, _vp]),
+    "hm_autotune_grad_workspace": (_i, [_vp, _i, _i, ctypes.POINTER(_sz)]),
+    "hm_autotune_grad": (_i, [_vp, _vp, _i, _i, ctypes.c_double, _vp, _vp, _vp, _sz, _vp]),
+    "hm_autotune_batched": (_i, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_i), _i, _i, _vp, _vp, _sz, _vp]),
     "hm_tune_clear": (_i, [_vp]),
     "hm_profile_enable": (_i, [_i]),
     "hm_profile_reset": (_i, []),
@@ -328,6 +333,57 @@ def autotune(psi, sample_shifts: int = 16384, *, ctx: Context | None = None, str
     ws = _workspace(b.value, psi.device, stream)
     _check(lib().hm_autotune(ctx.h, _ptr(psi), n, dt, sample_shifts, _ptr(ws), ws.numel(), _stream(stream)))
     return tuned_plan(n, dt, ctx=ctx)
+
+
+def autotune_mana(psi, sample_shifts: int = 4096, *, ctx: Context | None = None, stream=None):
+    """Time the mana launch plans for this qutrit state's size and dtype and keep the fastest in ctx."""
+    ctx = ctx or default_context()
+    psi, n = _state(psi, 3)
+    dt = _dtype_code(psi)
+    b = _sz(0)
+    _check(lib().hm_autotune_mana_workspace(ctx.h, n, dt, ctypes.byref(b)))
+    ws = _workspace(b.value, psi.device, stream)
+    _check(lib().hm_autotune_mana(ctx.h, _ptr(psi), n, dt, sample_shifts, _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def autotune_grad(psi, q: float = 2.0, *, ctx: Context | None = None, stream=None):
+    """Time the gradient paths for this state's size and dtype and keep the fastest in ctx."""
+    torch = _torch()
+    ctx = ctx or default_context()
+    psi, n = _state(psi, 2)
+    dt = _dtype_code(psi)
+    b = _sz(0)
+    _check(lib().hm_autotune_grad_workspace(ctx.h, n, dt, ctypes.byref(b)))
+    ws = _workspace(b.value, psi.device, stream)
+    out = torch.empty(2, dtype=torch.float64, device=psi.device)
+    grad = torch.empty_like(psi)
+    _check(lib().hm_autotune_grad(ctx.h, _ptr(psi), n, dt, float(q), _ptr(out), _ptr(grad), _ptr(ws), ws.numel(),
+                                  _stream(stream)))
+
+
+def autotune_batched(states, *, ctx: Context | None = None, stream=None):
+    """Time hm_sre_batched's launch forms on these states and keep the faster in ctx."""
+    torch = _torch()
+    ctx = ctx or default_context()
+    sts, ns = [], []
+    for s in states:
+        s, n = _state(s, 2)
+        sts.append(s)
+        ns.append(n)
+    dt = _dtype_code(sts[0])
+    B = len(sts)
+    ns_c = (_i * B)(*ns)
+    ptrs = (_vp * B)(*[s.data_ptr() for s in sts])
+    need = 0
+    for mode in (1, 2):
+        c2 = Context()
+        c2.set_option(OPT_BATCH_LAUNCH, mode)
+        b = _sz(0)
+        _check(lib().hm_sre_batched_workspace(c2.h, ns_c, B, dt, 1, ctypes.byref(b)))
+        need = max(need, b.value)
+    ws = _workspace(need, sts[0].device, stream)
+    out = torch.empty((B, 2), dtype=torch.float64, device=sts[0].device)
+    _check(lib().hm_autotune_batched(ctx.h, ptrs, ns_c, B, dt, _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
 
 
 def tuned_plan(n: int, dtype_code: int, *, ctx: Context | None = None) -> dict:

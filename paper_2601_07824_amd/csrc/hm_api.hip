@@ -81,6 +81,34 @@ static int fill_dev(double *p, int64_t n, double v, hipStream_t st) {
   return hipPeekAtLastError() == hipSuccess ? OK : fail(E_HIP, "fill launch: %s", hipGetErrorString(hipGetLastError()));
 }
 
+// Times fn() once after a warm-up call, on stream st (milliseconds).
+template <typename F>
+static int time_once_api(hipStream_t st, F fn, float *ms) {
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return fail(E_HIP, "autotune: hipEventCreate failed");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(E_HIP, "autotune: hipEventCreate failed");
+  }
+  int err = fn();
+  if (!err && hipEventRecord(e0, st) != hipSuccess) err = fail(E_HIP, "autotune: hipEventRecord failed");
+  if (!err) err = fn();
+  if (!err && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+    err = fail(E_HIP, "autotune: %s", hipGetErrorString(hipGetLastError()));
+  if (!err) (void)hipEventElapsedTime(ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return err;
+}
+
+// Autotuners of the mana, gradient plans (hm_tune.hip).
+size_t mana_autotune_workspace(const hm_context *h, int n, int dbl);
+int mana_autotune(hm_context *h, const void *psi, int n, int dbl, int64_t sample, void *ws, size_t ws_bytes,
+                  hipStream_t st);
+size_t grad_autotune_workspace(const hm_context *h, int n, int dbl);
+int grad_autotune(hm_context *h, const void *psi, int n, int dbl, double q, void *out, void *grad, void *ws,
+                  size_t ws_bytes, hipStream_t st);
+
 // Monte Carlo by thermodynamic integration (hm_mc.hip).
 int mc_check(int n, const hm_mc_params *prm);
 int mc_workspace(const SrePlan &p, const hm_mc_params *prm, size_t *bytes);
@@ -204,12 +232,12 @@ hm_status hm_workspace_size(hm_handle h, hm_op op, int n, hm_dtype dtype, int n_
       return HM_OK;
     case HM_OP_SRE_GRAD:
       if (n < 1 || n > 20) return (hm_status)fail(E_SIZE, "gradient: n = %d outside [1, 20]", n);
-      HM_TRY(sre_grad_workspace(plan_opts(h, n, dbl), n, dbl, bytes));
+      HM_TRY(sre_grad_workspace(grad_opts(h, n, dbl), n, dbl, bytes));
       return HM_OK;
     case HM_OP_SRE_GRAD_BATCHED:
       if (n < 1 || n > 20) return (hm_status)fail(E_SIZE, "gradient: n = %d outside [1, 20]", n);
       if (count < 1 || count > INT32_MAX) return (hm_status)fail(E_ARG, "gradient: count = %lld outside [1, 2^31)", (long long)count);
-      HM_TRY(sre_grad_batched_workspace(plan_opts(h, n, dbl), n, dbl, (int)count, bytes));
+      HM_TRY(sre_grad_batched_workspace(grad_opts(h, n, dbl), n, dbl, (int)count, bytes));
       return HM_OK;
     case HM_OP_SRE_SAMPLED: {
       if (count < 2) return (hm_status)fail(E_ARG, "sampled: count = %lld < 2", (long long)count);
@@ -220,7 +248,10 @@ hm_status hm_workspace_size(hm_handle h, hm_op op, int n, hm_dtype dtype, int n_
     }
     case HM_OP_MANA: {
       if (n < 1 || n > 16) return (hm_status)fail(E_SIZE, "mana: n = %d outside [1, 16]", n);
-      HM_TRY(mana_workspace(n, dbl, h->opts.batch, (int)h->opts.streams, bytes));
+      int64_t mb;
+      int ms;
+      mana_opts(h, n, dbl, &mb, &ms);
+      HM_TRY(mana_workspace(n, dbl, mb, ms, bytes));
       return HM_OK;
     }
   }
@@ -317,7 +348,7 @@ hm_status hm_sre_grad(hm_handle h, const void *psi, int n, hm_dtype dtype, doubl
   HM_TRY(check_ptr(grad, psi_align(dtype), "grad"));
   HM_TRY(check_ptr(out, 8, "out"));
   if (!(q > 0.0) || !isfinite(q) || q == 1.0) return (hm_status)fail(E_ARG, "gradient: q = %g must be positive, finite and != 1", q);
-  const PlanOpts o = plan_opts(h, n, dtype == HM_C128);
+  const PlanOpts o = grad_opts(h, n, dtype == HM_C128);
   size_t need = 0;
   HM_TRY(sre_grad_workspace(o, n, dtype == HM_C128, &need));
   HM_TRY(check_ws(ws, ws_bytes, need));
@@ -339,7 +370,7 @@ hm_status hm_sre_grad_batched(hm_handle h, const void *const *psis, int n, int b
   }
   HM_TRY(check_ptr(out, 8, "out"));
   if (!(q > 0.0) || !isfinite(q) || q == 1.0) return (hm_status)fail(E_ARG, "gradient: q = %g must be positive, finite and != 1", q);
-  const PlanOpts o = plan_opts(h, n, dtype == HM_C128);
+  const PlanOpts o = grad_opts(h, n, dtype == HM_C128);
   size_t need = 0;
   HM_TRY(sre_grad_batched_workspace(o, n, dtype == HM_C128, batch, &need));
   HM_TRY(check_ws(ws, ws_bytes, need));
@@ -355,7 +386,8 @@ static constexpr int BATCH_LAUNCH_DEFAULT = 1;
 // size class / one after another on the same workspace after it.
 static void batched_split(hm_handle h, const int *ns, int batch, int dbl, std::vector<int> *pers,
                           std::vector<int> *rest) {
-  const int mode = h->opts.batch_launch ? h->opts.batch_launch : BATCH_LAUNCH_DEFAULT;
+  const int mode = h->opts.batch_launch ? h->opts.batch_launch
+                   : h->tuned_batch_launch ? h->tuned_batch_launch : BATCH_LAUNCH_DEFAULT;
   for (int i = 0; i < batch; ++i) {
     if (mode == 2) {
       rest->push_back(i);
@@ -527,6 +559,80 @@ hm_status hm_autotune(hm_handle h, const void *psi, int n, hm_dtype dtype, int64
   return (hm_status)sre_autotune(h, psi, n, dtype == HM_C128, sample_shifts, ws, ws_bytes, stream, nullptr);
 }
 
+hm_status hm_autotune_mana_workspace(hm_handle h, int n, hm_dtype dtype, size_t *bytes) {
+  g_err[0] = 0;
+  if (!h || !bytes) return (hm_status)fail(E_ARG, "h or bytes is NULL");
+  HM_TRY(check_dtype(dtype));
+  if (n < 1 || n > 16) return (hm_status)fail(E_SIZE, "mana: n = %d outside [1, 16]", n);
+  *bytes = mana_autotune_workspace(h, n, dtype == HM_C128);
+  return HM_OK;
+}
+
+hm_status hm_autotune_mana(hm_handle h, const void *psi, int n, hm_dtype dtype, int64_t sample_shifts, void *ws,
+                           size_t ws_bytes, hipStream_t stream) {
+  g_err[0] = 0;
+  if (!h) return (hm_status)fail(E_ARG, "h is NULL");
+  HM_TRY(check_dtype(dtype));
+  if (n < 1 || n > 16) return (hm_status)fail(E_SIZE, "mana: n = %d outside [1, 16]", n);
+  HM_TRY(check_ptr(psi, psi_align(dtype), "psi"));
+  HM_TRY(check_ws(ws, ws_bytes, 256));
+  return (hm_status)mana_autotune(h, psi, n, dtype == HM_C128, sample_shifts, ws, ws_bytes, stream);
+}
+
+hm_status hm_autotune_grad_workspace(hm_handle h, int n, hm_dtype dtype, size_t *bytes) {
+  g_err[0] = 0;
+  if (!h || !bytes) return (hm_status)fail(E_ARG, "h or bytes is NULL");
+  HM_TRY(check_dtype(dtype));
+  if (n < 1 || n > 20) return (hm_status)fail(E_SIZE, "gradient: n = %d outside [1, 20]", n);
+  *bytes = grad_autotune_workspace(h, n, dtype == HM_C128);
+  return HM_OK;
+}
+
+hm_status hm_autotune_grad(hm_handle h, const void *psi, int n, hm_dtype dtype, double q, double *out, void *grad,
+                           void *ws, size_t ws_bytes, hipStream_t stream) {
+  g_err[0] = 0;
+  if (!h) return (hm_status)fail(E_ARG, "h is NULL");
+  HM_TRY(check_dtype(dtype));
+  if (n < 1 || n > 20) return (hm_status)fail(E_SIZE, "gradient: n = %d outside [1, 20]", n);
+  HM_TRY(check_ptr(psi, psi_align(dtype), "psi"));
+  HM_TRY(check_ptr(grad, psi_align(dtype), "grad"));
+  HM_TRY(check_ptr(out, 8, "out"));
+  if (!(q > 0.0) || !isfinite(q) || q == 1.0) return (hm_status)fail(E_ARG, "gradient: q = %g must be positive, finite and != 1", q);
+  HM_TRY(check_ws(ws, ws_bytes, 256));
+  return (hm_status)grad_autotune(h, psi, n, dtype == HM_C128, q, out, grad, ws, ws_bytes, stream);
+}
+
+hm_status hm_autotune_batched(hm_handle h, const void *const *psis, const int *ns, int batch, hm_dtype dtype,
+                              double *out, void *ws, size_t ws_bytes, hipStream_t stream) {
+  g_err[0] = 0;
+  if (!h) return (hm_status)fail(E_ARG, "h is NULL");
+  HM_TRY(check_dtype(dtype));
+  if (h->opts.batch_launch) return (hm_status)fail(E_ARG, "batched autotune: HM_OPT_BATCH_LAUNCH is fixed on the handle");
+  const double q2 = 2.0;
+  float best = -1.f;
+  int pick = 0;
+  for (int mode : {1, 2}) {
+    h->opts.batch_launch = mode;
+    size_t need = 0;
+    hm_status st = hm_sre_batched_workspace(h, ns, batch, dtype, 1, &need);
+    if (st == HM_OK && need > ws_bytes) st = HM_E_WORKSPACE;
+    float ms = 0.f;
+    int err = st;
+    if (!err)
+      err = time_once_api(stream, [&]() { return (int)hm_sre_batched(h, psis, ns, batch, dtype, &q2, 1, out, ws, ws_bytes, stream); }, &ms);
+    h->opts.batch_launch = 0;
+    if (err == E_WORKSPACE) continue;
+    if (err) return (hm_status)err;
+    if (best < 0.f || ms < best) {
+      best = ms;
+      pick = mode;
+    }
+  }
+  if (!pick) return (hm_status)fail(E_WORKSPACE, "batched autotune: no launch form fits a workspace of %zu bytes", ws_bytes);
+  h->tuned_batch_launch = pick;
+  return HM_OK;
+}
+
 hm_status hm_tune_query(hm_handle h, int n, hm_dtype dtype, int64_t *opts, double *ms_per_shift) {
   g_err[0] = 0;
   if (!h || !opts) return (hm_status)fail(E_ARG, "h or opts is NULL");
@@ -546,6 +652,9 @@ hm_status hm_tune_clear(hm_handle h) {
   g_err[0] = 0;
   if (!h) return (hm_status)fail(E_ARG, "h is NULL");
   h->tuned.clear();
+  h->tuned_mana.clear();
+  h->tuned_grad.clear();
+  h->tuned_batch_launch = 0;
   return HM_OK;
 }
 
@@ -560,10 +669,13 @@ hm_status hm_mana(hm_handle h, const void *psi, int n, hm_dtype dtype, double *o
   uint64_t D = 1;
   for (int i = 0; i < n; ++i) D *= 3;
   size_t need = 0;
-  HM_TRY(mana_workspace(n, dtype == HM_C128, h->opts.batch, (int)h->opts.streams, &need));
+  int64_t mb;
+  int ms;
+  mana_opts(h, n, dtype == HM_C128, &mb, &ms);
+  HM_TRY(mana_workspace(n, dtype == HM_C128, mb, ms, &need));
   HM_TRY(check_ws(ws, ws_bytes, need));
   HM_TRY(norm_ok(h, psi, 3, n, dtype, stream));
-  return (hm_status)mana_launch(n, dtype == HM_C128, h->opts.batch, (int)h->opts.streams, psi, 0, D, nullptr, out, ws, ws_bytes, stream);
+  return (hm_status)mana_launch(n, dtype == HM_C128, mb, ms, psi, 0, D, nullptr, out, ws, ws_bytes, stream);
 }
 
 hm_status hm_mana_partial(hm_handle h, const void *psi, int n, hm_dtype dtype, uint64_t a0, uint64_t a1, double *sums,
@@ -578,11 +690,14 @@ hm_status hm_mana_partial(hm_handle h, const void *psi, int n, hm_dtype dtype, u
   for (int i = 0; i < n; ++i) D *= 3;
   if (a0 > a1 || a1 > D) return (hm_status)fail(E_ARG, "shift range [%llu, %llu) not inside [0, 3^%d]", (unsigned long long)a0, (unsigned long long)a1, n);
   size_t need = 0;
-  HM_TRY(mana_workspace(n, dtype == HM_C128, h->opts.batch, (int)h->opts.streams, &need));
+  int64_t mb;
+  int ms;
+  mana_opts(h, n, dtype == HM_C128, &mb, &ms);
+  HM_TRY(mana_workspace(n, dtype == HM_C128, mb, ms, &need));
   HM_TRY(check_ws(ws, ws_bytes, need));
   HM_TRY(norm_ok(h, psi, 3, n, dtype, stream));
   if (a1 == a0) return (hm_status)fill_dev(sums, 3, 0.0, stream);
-  return (hm_status)mana_launch(n, dtype == HM_C128, h->opts.batch, (int)h->opts.streams, psi, a0, a1, sums, nullptr, ws, ws_bytes, stream);
+  return (hm_status)mana_launch(n, dtype == HM_C128, mb, ms, psi, a0, a1, sums, nullptr, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

@@ -106,6 +106,20 @@ struct TunedPlan {
   PlanOpts opts;
   double ms_per_shift;
 };
+// Mana plan chosen by the autotuner for one (qutrit count, dtype): X-shifts per two-pass launch pair
+// and streams.
+struct TunedMana {
+  int n, dbl;
+  int64_t batch;
+  int streams;
+  double ms_per_shift;
+};
+// Gradient path chosen by the autotuner for one (qubit count, dtype): 1 resident, 2 two-pass.
+struct TunedGrad {
+  int n, dbl;
+  int path;
+  double ms;
+};
 
 }  // namespace hm
 
@@ -113,7 +127,10 @@ struct TunedPlan {
 struct hm_context {
   hm::PlanOpts opts;
   std::vector<hm::TunedPlan> tuned;
-  int check_norm = 0;  // HM_OPT_CHECK_NORM
+  std::vector<hm::TunedMana> tuned_mana;
+  std::vector<hm::TunedGrad> tuned_grad;
+  int tuned_batch_launch = 0;  // launch form of hm_sre_batched picked by hm_autotune_batched
+  int check_norm = 0;          // HM_OPT_CHECK_NORM
 };
 
 namespace hm {
@@ -127,6 +144,9 @@ size_t sre_autotune_workspace(const hm_context *h, int n, int dbl, int64_t sampl
 // Options for planning (n, dbl) on handle h: every field the caller left automatic (0) is taken
 // from the autotuner's entry for (n, dbl), if there is one.
 PlanOpts plan_opts(const hm_context *h, int n, int dbl);
+// The same for mana (X-shifts per launch pair, streams) and the gradient (path).
+void mana_opts(const hm_context *h, int n, int dbl, int64_t *batch, int *streams);
+PlanOpts grad_opts(const hm_context *h, int n, int dbl);
 
 // Fills a plan; returns OK or E_UNSUPPORTED/E_SIZE with a message.
 int sre_plan(int N, int dbl, const PlanOpts &o, SrePlan *p);

@@ -1,11 +1,13 @@
-// hm_tune.hip -- on-device autotuner for the qubit SRE plan.
+// hm_tune.hip -- on-device autotuner for the launch plans.
 //
 // The two-pass kernels have several free choices (X-shifts per launch, LDS staging, sequential or
 // pipelined launches, the row/column split of the folded index bits), and which one is fastest
 // depends on n, the dtype and the memory level the exchange lands in.  The tuner times each
 // candidate plan on the caller's state over a prefix of the X-shifts (hipEvents on the caller's
 // stream), keeps the fastest in the handle, and planning on that handle then fills every option
-// the caller left automatic from that entry.
+// the caller left automatic from that entry.  The same is done for the mana plan (X-shifts per
+// launch pair, one or two streams), the gradient (workgroup-resident or two-pass kernels where
+// both exist) and the batched forward (one persistent launch or one launch per size class).
 #include <hip/hip_runtime.h>
 #include <string.h>
 
@@ -31,6 +33,144 @@ PlanOpts plan_opts(const hm_context *h, int n, int dbl) {
     break;
   }
   return o;
+}
+
+void mana_opts(const hm_context *h, int n, int dbl, int64_t *batch, int *streams) {
+  *batch = h->opts.batch;
+  *streams = h->opts.streams;
+  for (const auto &t : h->tuned_mana)
+    if (t.n == n && t.dbl == dbl) {
+      if (!*batch) *batch = t.batch;
+      if (!*streams) *streams = t.streams;
+      break;
+    }
+}
+
+PlanOpts grad_opts(const hm_context *h, int n, int dbl) {
+  PlanOpts o = h->opts;
+  if (!o.force_path)
+    for (const auto &t : h->tuned_grad)
+      if (t.n == n && t.dbl == dbl) {
+        o.force_path = t.path;
+        break;
+      }
+  return o;
+}
+
+// Times fn() once after a warm-up call, on stream st (milliseconds).
+template <typename F>
+static int time_once(hipStream_t st, F fn, float *ms) {
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return fail(E_HIP, "autotune: hipEventCreate failed");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(E_HIP, "autotune: hipEventCreate failed");
+  }
+  int err = fn();
+  if (!err && hipEventRecord(e0, st) != hipSuccess) err = fail(E_HIP, "autotune: hipEventRecord failed");
+  if (!err) err = fn();
+  if (!err && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+    err = fail(E_HIP, "autotune: %s", hipGetErrorString(hipGetLastError()));
+  if (!err) (void)hipEventElapsedTime(ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return err;
+}
+
+// ---- mana ----------------------------------------------------------------------------------------
+// Candidates: exchange of 128, 192 or 256 MiB per launch pair on one or two streams (one plan for
+// the workgroup-resident sizes).  Options fixed on the handle are kept.
+static std::vector<std::pair<int64_t, int>> mana_candidates(const hm_context *h, int n, int dbl) {
+  std::vector<std::pair<int64_t, int>> c;
+  uint64_t D = 1;
+  for (int i = 0; i < n; ++i) D *= 3;
+  const size_t per_pair = (size_t)D * (dbl ? 16 : 8);
+  for (int mib : {128, 192, 256})
+    for (int streams : {1, 2}) {
+      int64_t b = h->opts.batch ? h->opts.batch : 2 * (int64_t)(((size_t)mib << 20) / per_pair);
+      if (b < 2) b = 2;
+      const int sm = h->opts.streams ? h->opts.streams : streams;
+      bool dup = false;
+      for (auto &e : c) dup |= e.first == b && e.second == sm;
+      size_t bytes;
+      if (!dup && mana_workspace(n, dbl, b, sm, &bytes) == OK) c.push_back({b, sm});
+    }
+  return c;
+}
+
+size_t mana_autotune_workspace(const hm_context *h, int n, int dbl) {
+  size_t need = 256, b;
+  for (auto &c : mana_candidates(h, n, dbl))
+    if (mana_workspace(n, dbl, c.first, c.second, &b) == OK && b > need) need = b;
+  return need;
+}
+
+int mana_autotune(hm_context *h, const void *psi, int n, int dbl, int64_t sample, void *ws, size_t ws_bytes,
+                  hipStream_t st) {
+  uint64_t D = 1;
+  for (int i = 0; i < n; ++i) D *= 3;
+  uint64_t k = sample > 0 ? (uint64_t)sample : 4096;
+  if (k > D) k = D;
+  TunedMana best{};
+  best.ms_per_shift = -1.0;
+  int tried = 0;
+  for (auto &c : mana_candidates(h, n, dbl)) {
+    size_t b;
+    if (mana_workspace(n, dbl, c.first, c.second, &b) != OK || b > ws_bytes) continue;
+    float ms = 0.f;
+    int err = time_once(st, [&]() { return mana_launch(n, dbl, c.first, c.second, psi, 0, k, nullptr, nullptr, ws, ws_bytes, st); }, &ms);
+    if (err) return err;
+    ++tried;
+    const double per = (double)ms / (double)k;
+    if (best.ms_per_shift < 0 || per < best.ms_per_shift) best = TunedMana{n, dbl, c.first, c.second, per};
+  }
+  if (!tried) return fail(E_WORKSPACE, "mana autotune: no candidate plan fits a workspace of %zu bytes", ws_bytes);
+  for (auto it = h->tuned_mana.begin(); it != h->tuned_mana.end(); ++it)
+    if (it->n == n && it->dbl == dbl) {
+      h->tuned_mana.erase(it);
+      break;
+    }
+  h->tuned_mana.push_back(best);
+  return OK;
+}
+
+// ---- gradient -------------------------------------------------------------------------------------
+size_t grad_autotune_workspace(const hm_context *h, int n, int dbl) {
+  size_t need = 256;
+  for (int path : {1, 2}) {
+    PlanOpts o = h->opts;
+    if (!o.force_path) o.force_path = path;
+    size_t b;
+    if (sre_grad_workspace(o, n, dbl, &b) == OK && b > need) need = b;
+  }
+  return need;
+}
+
+int grad_autotune(hm_context *h, const void *psi, int n, int dbl, double q, void *out, void *grad, void *ws,
+                  size_t ws_bytes, hipStream_t st) {
+  TunedGrad best{n, dbl, 0, -1.0};
+  int tried = 0;
+  for (int path : {1, 2}) {
+    PlanOpts o = h->opts;
+    if (o.force_path && o.force_path != path) continue;
+    o.force_path = path;
+    size_t b;
+    if (sre_grad_workspace(o, n, dbl, &b) != OK || b > ws_bytes) continue;
+    float ms = 0.f;
+    int err = time_once(st, [&]() { return sre_grad_launch(o, n, dbl, psi, q, (double *)out, grad, ws, ws_bytes, st); }, &ms);
+    if (err == E_UNSUPPORTED || err == E_SIZE) continue;  // no kernels of this path for n
+    if (err) return err;
+    ++tried;
+    if (best.ms < 0 || ms < best.ms) best = TunedGrad{n, dbl, path, ms};
+  }
+  if (!tried) return fail(E_WORKSPACE, "gradient autotune: no path fits a workspace of %zu bytes", ws_bytes);
+  for (auto it = h->tuned_grad.begin(); it != h->tuned_grad.end(); ++it)
+    if (it->n == n && it->dbl == dbl) {
+      h->tuned_grad.erase(it);
+      break;
+    }
+  h->tuned_grad.push_back(best);
+  return OK;
 }
 
 // Candidate plans for (n, dbl): the workgroup-resident kernel when it applies, and two-pass plans

@@ -335,3 +335,24 @@ def test_mc_argument_errors(L, h):
     assert L.hm_sre_mc(h, good, 10, 0, ctypes.byref(prm), None, good, good, good, good, good, 1 << 40, None) == HM_E_ARG
     assert L.hm_sre_mc(h, good, 27, 0, ctypes.byref(prm), good, good, good, good, good, good, 1 << 40, None) == HM_E_SIZE
     assert L.hm_sre_mc(h, good, 10, 0, ctypes.byref(prm), good, good, good, good, good, good, 16, None) == HM_E_WORKSPACE
+
+
+def test_autotune_other_plans_argument_errors(L, h):
+    good, ws = P(0x100000), P(0x200000)
+    b = ctypes.c_size_t(0)
+    assert L.hm_autotune_mana_workspace(h, 12, 0, ctypes.byref(b)) == HM_OK and b.value > 256
+    assert L.hm_autotune_mana_workspace(h, 17, 0, ctypes.byref(b)) == HM_E_SIZE
+    assert L.hm_autotune_mana(h, None, 12, 0, 0, ws, 1 << 30, None) == HM_E_ARG
+    assert L.hm_autotune_mana(h, good, 0, 0, 0, ws, 1 << 30, None) == HM_E_SIZE
+    assert L.hm_autotune_grad_workspace(h, 13, 0, ctypes.byref(b)) == HM_OK and b.value > 256
+    assert L.hm_autotune_grad_workspace(h, 21, 0, ctypes.byref(b)) == HM_E_SIZE
+    assert L.hm_autotune_grad(h, good, 13, 0, 1.0, good, good, ws, 1 << 30, None) == HM_E_ARG  # q = 1
+    assert L.hm_autotune_grad(h, good, 13, 0, 2.0, good, None, ws, 1 << 30, None) == HM_E_ARG
+    hh = P()
+    assert L.hm_create(ctypes.byref(hh)) == HM_OK
+    assert L.hm_set_option(hh, 10, 2) == HM_OK  # HM_OPT_BATCH_LAUNCH fixed: nothing to tune
+    ns = (ctypes.c_int * 1)(8)
+    ps = (P * 1)(good)
+    assert L.hm_autotune_batched(hh, ps, ns, 1, 0, good, ws, 1 << 30, None) == HM_E_ARG
+    assert L.hm_set_option(hh, 10, 3) == HM_E_ARG
+    L.hm_destroy(hh)
