@@ -55,7 +55,7 @@ def roofline(fam: str, N: int, vals_per_launch: float, t_launch: float, launches
     workgroup-resident kernel touches device memory only for the state and is bound by FP32 VALU
     arithmetic."""
     nf = N - 1
-    nl = (nf + 1) // 2
+    nl = (plan or {}).get("row_bits") or (nf + 1) // 2  # index bits of the row pass in the timed plan
     nh = nf - nl
     xbytes = {"sre_rowpass_write": 8.0, "sre_colpass": 8.0, "sre_pair": 16.0}.get(fam)
     mix = sre_kernel_mix(N, fam if fam != "sre_pair" else "sre_rowpass_write", nl, nh)
@@ -104,6 +104,16 @@ def traffic_for(kernel: str, workload: str, plan: dict | None):
         return None
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(psi_w, N: int, target_s: float = 12.0):
     import oracle
     cores = oracle.get_threads()
@@ -117,6 +127,7 @@ def cpu_baseline(psi_w, N: int, target_s: float = 12.0):
     oracle.sre_fwht_sums(psi_w, (2.0,), 0, k2)
     dt = time.perf_counter() - t
     return {"value": k2 * float(2 ** N) / dt, "unit": "Pauli expectations/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"X-shifts a in [0, {k2}) of the N={N} workload ({k2} of {2 ** N} rows, "
                       f"{k2 * 2 ** N:.3e} expectations, {dt:.1f} s, FP64 C + OpenMP)"}
 
@@ -131,27 +142,96 @@ def _timed(torch, fn, reps=1):
     return (time.perf_counter() - t) / reps, o
 
 
+GOLDEN = os.path.join(ROOT, "tests", "golden", "oracle_golden.json")
+
+
+def golden(key):
+    """FP64 oracle values stored by tests/golden/make_golden.py (None if not generated)."""
+    try:
+        return json.load(open(GOLDEN)).get(key)
+    except (OSError, ValueError):
+        return None
+
+
+def error_vs_oracle(got: float, key: str, index: int = 0):
+    g = golden(key)
+    if not g:
+        return None
+    want = g["values"][index]
+    return {"oracle": want, "abs": abs(got - want), "rel": abs(got - want) / abs(want), "golden": key}
+
+
+def profiled(hm, torch, fn, every=1):
+    """Runs fn() once with every-th launch of each kernel family timed on its stream; returns
+    (wall seconds, fn's result, {family: (launches, timed, ms)})."""
+    fn()
+    torch.cuda.synchronize()
+    hm.profile_reset()
+    hm.profile_enable(every)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    o = fn()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    hm.profile_enable(False)
+    return dt, o, hm.profile_read()
+
+
+def exchange_roofline(prof, fam_bytes: dict, work_values: float):
+    """Roofline of the dominant exchange kernel of a two-pass run: bytes per launch = the values it
+    moves (work_values / launches) x the bytes each value moves through device memory."""
+    est = {k: v[2] / max(v[1], 1) * v[0] for k, v in prof.items() if v[1] > 0 and k in fam_bytes}
+    if not est:
+        return None
+    fam = max(est, key=est.get)
+    launches, timed, tot_ms = prof[fam]
+    t_launch = tot_ms * 1e-3 / timed
+    bpl = work_values / launches * fam_bytes[fam]
+    return {"kernel": fam, "bound": "hbm", "launches": launches, "avg_launch_ms": round(t_launch * 1e3, 5),
+            "bytes_per_launch": bpl, "achieved": round(bpl / t_launch / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(bpl / t_launch / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def secondary(hm, S, torch, dev, psi, N):
     """The other rows of the metric, each timed once after a warm-up call (wall clock around the
     call, state resident; plans autotuned where noted): complex128 forward at the headline N
-    (tuned), mana at N = 12, fused forward + adjoint against the plain forwards at N = 13
-    (workgroup-resident gradient) and N = 18 (two-pass gradient), batches of 64 circuit states at
-    N = 12 and 16 (batched fused forward + adjoint, 64 single calls, FP64 forward), the batched form on 1024 states
-    of uneven size, and the Monte Carlo estimator at N = 24 (tuned)."""
+    (tuned, with the roofline of its dominant kernel), mana at N = 12 (tuned, roofline), fused
+    forward + adjoint against the plain forwards at N = 13 (workgroup-resident gradient) and N = 18
+    (two-pass gradient), batches of 64 circuit states at N = 12 and 16 (batched fused forward +
+    adjoint, 64 single calls, FP64 forward), the batched form on 1024 states of uneven size (one
+    persistent launch, and the autotuned launch form), the uniform-row Monte Carlo estimator at
+    N = 24, the thermodynamic-integration estimator at N = 16, 18, 20 against the exact value and at
+    N = 24, 26, and each result's error against the stored FP64 oracle values where they exist."""
     import numpy as np
     sec = {}
     try:
         x128 = torch.from_numpy(psi).to(dev)
         c128 = hm.Context()
         hm.autotune(x128, 16384, ctx=c128)
-        dt, o = _timed(torch, lambda: hm.sre(x128, (2.0,), ctx=c128))
-        sec["sre_fwd_c128_n%d" % N] = {"value": 4.0 ** N / dt, "unit": "Pauli expectations/s", "ms": dt * 1e3,
-                                        "M2": float(o[0].item())}
+        dt, o, prof = profiled(hm, torch, lambda: hm.sre(x128, (2.0,), ctx=c128), every=64)
+        m2 = float(o[0].item())
+        sec["sre_fwd_c128_n%d" % N] = {
+            "value": 4.0 ** N / dt, "unit": "Pauli expectations/s", "ms": dt * 1e3, "M2": m2,
+            "error_vs_oracle": error_vs_oracle(m2, "sre_brickwall_n%d_d%d_seed2020_c128" % (N, 2 * N), 1),
+            # 4^N / 2 folded FP64 complex values per evaluation, 16 B each written by the row pass and
+            # read by the column pass (both by the pipelined kernel)
+            "roofline": exchange_roofline(prof, {"sre_rowpass_write": 16.0, "sre_colpass": 16.0, "sre_pair": 32.0},
+                                          4.0 ** N / 2.0),
+            "plan": hm.tuned_plan(N, hm.HM_C128, ctx=c128)}
         del x128
         m = torch.from_numpy(S.to_c64_exact(S.gaussian_state(12, d=3, seed=1212))[0]).to(dev)
-        dt, o = _timed(torch, lambda: hm.mana(m))
-        sec["mana_n12_c64"] = {"value": 9.0 ** 12 / dt, "unit": "phase-space points/s", "ms": dt * 1e3,
-                               "mana": float(o[0].item())}
+        cm = hm.Context()
+        hm.autotune_mana(m, 4096, ctx=cm)
+        dt, o, prof = profiled(hm, torch, lambda: hm.mana(m, ctx=cm), every=16)
+        mana = float(o[0].item())
+        sec["mana_n12_c64"] = {
+            "value": 9.0 ** 12 / dt, "unit": "phase-space points/s", "ms": dt * 1e3, "mana": mana,
+            "error_vs_oracle": error_vs_oracle(mana, "mana_gauss_n12_seed1212_c64"),
+            # packed values: 9^12 / 2 per evaluation, 8 B each written by the row pass and read by the column pass
+            "roofline": exchange_roofline(prof, {"mana_rowpass_write": 8.0, "mana_colpass": 8.0}, 9.0 ** 12 / 2.0),
+            "roofline_whole": {"bytes": 9.0 ** 12 / 2.0 * 16.0, "achieved_GBs": 9.0 ** 12 / 2.0 * 16.0 / dt / 1e9,
+                               "frac": 9.0 ** 12 / 2.0 * 16.0 / dt / 1e9 / HBM_PEAK_GBS}}
+        del m
         ng = 13
         pg = S.ry_rz_cz_state(ng, np.random.default_rng(4013).uniform(0, 2 * math.pi, (2, 2, ng)))
         g64 = torch.from_numpy(S.to_c64_exact(pg)[0]).to(dev)
@@ -168,7 +248,7 @@ def secondary(hm, S, torch, dev, psi, N):
         for key, fn in (("sre_fwd_grad_c64_n18", lambda: hm.sre_grad(g64, 2.0)),
                         ("sre_fwd_c64_n18", lambda: hm.sre(g64, (2.0,))),
                         ("sre_fwd_c128_n18", lambda: hm.sre(g128, (2.0,)))):
-            dt, _ = _timed(torch, fn)
+            dt, o = _timed(torch, fn)
             sec[key] = {"value": 4.0 ** ng / dt, "unit": "Pauli expectations/s", "ms": dt * 1e3}
         for ng in (12, 16):
             # a batch of 64 seeded 2-layer RY/RZ + CZ circuit states: batched fused forward + adjoint,
@@ -190,7 +270,12 @@ def secondary(hm, S, torch, dev, psi, N):
                   for i, n in enumerate(ns)]
         dt, _ = _timed(torch, lambda: hm.sre_batched(states, (2.0,)))
         sec["sre_batched_1024_n10to16_c64"] = {"value": float(np.sum(4.0 ** ns)) / dt, "unit": "Pauli expectations/s",
-                                               "ms": dt * 1e3, "states": 1024}
+                                               "ms": dt * 1e3, "states": 1024, "launch": "one persistent launch"}
+        cb = hm.Context()
+        hm.autotune_batched(states, ctx=cb)
+        dt, _ = _timed(torch, lambda: hm.sre_batched(states, (2.0,), ctx=cb))
+        sec["sre_batched_1024_n10to16_c64_tuned"] = {"value": float(np.sum(4.0 ** ns)) / dt,
+                                                     "unit": "Pauli expectations/s", "ms": dt * 1e3, "states": 1024}
         del states
         g = torch.Generator(device="cpu").manual_seed(2424)
         v = torch.view_as_complex(torch.randn(2 ** 24, 2, generator=g, dtype=torch.float32)).to(dev)
@@ -201,6 +286,31 @@ def secondary(hm, S, torch, dev, psi, N):
         sec["sre_mc_n24_4096rows_c64"] = {"value": 4097 * 2.0 ** 24 / dt, "unit": "Pauli expectations/s",
                                           "ms": dt * 1e3, "M2_hat": float(o[0].item()),
                                           "stderr": float(o[1].item())}
+        # thermodynamic integration (L = 9 beta points x 32 chains, 600 Metropolis steps, 100 left out)
+        for nm in (16, 18, 20):
+            x = torch.from_numpy(S.to_c64_exact(S.brickwall_haar(nm, 2 * nm, seed=9500 + nm))[0]).to(dev)
+            exact = float(hm.sre(x, (2.0,))[0].item())
+            t = time.perf_counter()
+            out, _ = hm.sre_mc(x, 9, 32, 600, 100, seed=9600 + nm)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            sec["sre_mc_ti_n%d_c64" % nm] = {"M2_hat": float(out[0].item()), "dM2": float(out[1].item()),
+                                             "M2_exact": exact, "error": float(out[0].item()) - exact,
+                                             "rows": 9 * 32 * 601, "ms": dt * 1e3,
+                                             "value": 9 * 32 * 601 * 2.0 ** nm / dt, "unit": "Pauli expectations/s"}
+        for nm, steps in ((24, 400), (26, 200)):
+            g = torch.Generator(device="cpu").manual_seed(2400 + nm)
+            v = torch.view_as_complex(torch.randn(2 ** nm, 2, generator=g, dtype=torch.float32)).to(dev)
+            v /= torch.linalg.vector_norm(v)
+            t = time.perf_counter()
+            out, _ = hm.sre_mc(v, 17, 4, steps, steps // 8, seed=9700 + nm)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            sec["sre_mc_ti_n%d_c64" % nm] = {"M2_hat": float(out[0].item()), "dM2": float(out[1].item()),
+                                             "haar_mean": math.log2(2.0 ** nm + 3) - 2, "rows": 17 * 4 * (steps + 1),
+                                             "ms": dt * 1e3, "value": 17 * 4 * (steps + 1) * 2.0 ** nm / dt,
+                                             "unit": "Pauli expectations/s"}
+            del v
     except hm.HmError as e:
         sec["error"] = str(e)[:200]
     return sec
@@ -400,8 +510,9 @@ def main():
                                + (f"all 4^{N} Pauli strings" if not args.shifts else
                                   f"X-shifts [0, {shifts}) x 2^{N} Z-strings (profiling subset)"),
                    "parallelism": "none (1 GPU)"},
-        "result": ({"M2": float(res[0]), "lost_norm": float(res[1])} if not args.shifts else
-                   {"partial_sums": [float(v) for v in res]}),
+        "result": ({"M2": float(res[0]), "lost_norm": float(res[1]),
+                    "error_vs_oracle": error_vs_oracle(float(res[0]), "sre_brickwall_n%d_d%d_seed%d_c64" % (N, 2 * N, seed))}
+                   if not args.shifts else {"partial_sums": [float(v) for v in res]}),
         "kernel_ms_per_step": {k: round(est[k] / args.steps, 3) for k in est},
         "roofline": roof,
         "plan": plan,
