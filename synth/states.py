@@ -26,6 +26,7 @@ __all__ = [
     "random_clifford_state", "clifford_t_state", "t_plus_clifford_state", "F3", "D3", "SUM3",
     "random_qutrit_clifford_ops", "random_qutrit_clifford_state", "ry_rz_cz_state",
     "ry_rz_cz_state_torch", "uniform_rows", "parity_conserving_state", "to_c64_exact",
+    "random_density", "pure_density", "ops_unitary",
 ]
 
 
@@ -297,3 +298,32 @@ def to_c64_exact(psi: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
     """Cast to complex64 and return (c64 vector, the same values widened back to complex128)."""
     c64 = psi.astype(np.complex64)
     return c64, c64.astype(np.complex128)
+
+
+# ----------------------------------------------------------------------------------------------
+# Density matrices of qutrits (mixed-state mana)
+# ----------------------------------------------------------------------------------------------
+def random_density(n: int, d: int = 3, rank: int | None = None, seed: int = 0) -> np.ndarray:
+    """G G^dagger / tr with G a d^n x rank complex Ginibre matrix (rank d^n by default): a seeded
+    random mixed state, as a d^n x d^n complex128 matrix (row index = ket, little-endian digits)."""
+    g = rng(seed)
+    D = d ** n
+    r = D if rank is None else rank
+    G = g.standard_normal((D, r)) + 1j * g.standard_normal((D, r))
+    rho = G @ G.conj().T
+    return (rho / np.trace(rho).real).astype(np.complex128)
+
+
+def pure_density(psi: np.ndarray) -> np.ndarray:
+    return np.outer(psi, psi.conj())
+
+
+def ops_unitary(n: int, ops: list, d: int = 3) -> np.ndarray:
+    """The d^n x d^n unitary of a gate list (columns = images of the basis states)."""
+    D = d ** n
+    U = np.empty((D, D), dtype=np.complex128)
+    for c in range(D):
+        e = np.zeros(D, dtype=np.complex128)
+        e[c] = 1.0
+        U[:, c] = apply_ops(e, n, ops, d)
+    return U
