@@ -166,7 +166,8 @@ typedef enum {
   HM_OP_SRE_GRAD = 3,   /* hm_sre_grad (count ignored)                                       */
   HM_OP_MANA = 4,       /* hm_mana and hm_mana_partial (count ignored)                       */
   HM_OP_SRE_SAMPLED = 5, /* hm_sre_sampled; count = n_rows                                   */
-  HM_OP_SRE_GRAD_BATCHED = 6 /* hm_sre_grad_batched; count = batch                          */
+  HM_OP_SRE_GRAD_BATCHED = 6, /* hm_sre_grad_batched; count = batch                         */
+  HM_OP_MANA_MIXED = 7   /* hm_mana_mixed (count ignored)                                     */
 } hm_op;
 hm_status hm_workspace_size(hm_handle h, hm_op op, int n, hm_dtype dtype, int n_q, int64_t count,
                             size_t *bytes);
@@ -333,6 +334,25 @@ hm_status hm_mana(hm_handle h, const void *psi, int n, hm_dtype dtype, double *o
 hm_status hm_mana_partial(hm_handle h, const void *psi, int n, hm_dtype dtype, uint64_t a0,
                           uint64_t a1, double *sums, void *ws, size_t ws_bytes, hipStream_t stream);
 
+
+/* Mana of a mixed state (Sec. "Mana of mixed states via a fast tensor-product transform", Eq.
+ * MN_factor_mana and its Algorithm): all 9^n values w_u = Tr(rho A_u) as the tensor power of a 9 x 9
+ * single-qutrit matrix applied to the reordered density matrix, one HBM-streaming pass per qutrit.
+ * rho: device, 3^n x 3^n row-major (rho[r 3^n + c] = <r|rho|c>, qutrit k = base-3 digit k of r and c),
+ * Hermitian (not checked; the imaginary parts of w are dropped).  out: device, 3 doubles
+ * = {mana = log2(sum_u |w_u| / 3^n), sum_u W(u) = Tr rho, 3^n sum_u W(u)^2 = Tr rho^2} with
+ * W = w / 3^n.  1 <= n <= 10.  Workspace: hm_workspace_size(HM_OP_MANA_MIXED): the reordered
+ * 9^n-value copy of rho (HM_C128 at n = 10: 56 GB) plus 2 x 3^n digit tables. */
+hm_status hm_mana_mixed(hm_handle h, const void *rho, int n, hm_dtype dtype, double *out, void *ws, size_t ws_bytes,
+                        hipStream_t stream);
+
+/* Reduced density matrix of a pure state on its first n_a qutrits (base-3 digits 0..n_a-1 of the
+ * index; the others traced out): rho[i 3^n_a + j] = sum_b psi[i + 3^n_a b] conj(psi[j + 3^n_a b]),
+ * summed in FP64, stored in the state's dtype, row-major 3^n_a x 3^n_a (device).  The subsystem
+ * mana of the paper's examples is hm_mana_mixed of this matrix.  1 <= n_a <= min(n, 10), n <= 16.
+ * No workspace. */
+hm_status hm_reduced_density(hm_handle h, const void *psi, int n, int n_a, hm_dtype dtype, void *rho,
+                             hipStream_t stream);
 
 /* ------------------------------------------------------------------------------------------ */
 /* Kernel timing (diagnostics)                                                                 */

@@ -18,7 +18,7 @@ from typing import Sequence
 
 __all__ = [
     "HmError", "lib", "lib_path", "Context", "default_context", "sre", "sre_partial", "sre_finalize",
-    "sre_rows", "sre_row_values", "sre_noalloc", "sre_mc", "McParams", "mc_random_inputs", "sre_grad", "sre_grad_batched", "SRE", "SREBatched", "sre_batched", "sre_sampled", "autotune", "autotune_mana", "autotune_grad", "autotune_batched", "tuned_plan", "mana", "mana_partial", "workspace_size",
+    "sre_rows", "sre_row_values", "sre_noalloc", "sre_mc", "McParams", "mc_random_inputs", "sre_grad", "sre_grad_batched", "SRE", "SREBatched", "sre_batched", "sre_sampled", "autotune", "autotune_mana", "autotune_grad", "autotune_batched", "tuned_plan", "mana", "mana_partial", "mana_mixed", "reduced_density_matrix", "workspace_size",
     "HM_C64", "HM_C128", "profile_enable", "profile_reset", "profile_read", "OP_SRE", "OP_SRE_ROWS", "OP_ROW_VALUES", "OP_SRE_GRAD", "OP_MANA",
     "OP_SRE_SAMPLED", "OP_SRE_GRAD_BATCHED", "EXPORTED_SYMBOLS",
 ]
@@ -28,6 +28,7 @@ lib_path = os.path.join(_HERE, "libhmag.so")
 
 HM_C64, HM_C128 = 0, 1
 OP_SRE, OP_SRE_ROWS, OP_ROW_VALUES, OP_SRE_GRAD, OP_MANA, OP_SRE_SAMPLED, OP_SRE_GRAD_BATCHED = 0, 1, 2, 3, 4, 5, 6
+OP_MANA_MIXED = 7
 OPT_FORCE_PATH, OPT_BATCH_SHIFTS, OPT_ROW_RB, OPT_COL_RB, OPT_ROW_BITS, OPT_PIPELINE, OPT_LDS_SPLIT, OPT_STREAMS = \
     1, 2, 3, 4, 5, 6, 7, 8
 OPT_CHECK_NORM = 9
@@ -59,6 +60,8 @@ _SIGS = {
                                  _vp, _sz, _vp]),
     "hm_mana": (_i, [_vp, _vp, _i, _i, _vp, _vp, _sz, _vp]),
     "hm_mana_partial": (_i, [_vp, _vp, _i, _i, _u64, _u64, _vp, _vp, _sz, _vp]),
+    "hm_mana_mixed": (_i, [_vp, _vp, _i, _i, _vp, _vp, _sz, _vp]),
+    "hm_reduced_density": (_i, [_vp, _vp, _i, _i, _i, _vp, _vp]),
     "hm_sre_batched_workspace": (_i, [_vp, ctypes.POINTER(_i), _i, _i, _i, ctypes.POINTER(_sz)]),
     "hm_sre_batched": (_i, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_i), _i, _i, _dp, _i, _vp, _vp, _sz, _vp]),
     "hm_sre_sampled": (_i, [_vp, _vp, _i, _i, _vp, _i64, _vp, _vp, _sz, _vp]),
@@ -646,3 +649,37 @@ def mana_partial(psi, a0: int = 0, a1: int | None = None, *, ctx: Context | None
     ws = _workspace(workspace_size(OP_MANA, n, dt, 1, 0, ctx), psi.device, stream)
     _check(lib().hm_mana_partial(ctx.h, _ptr(psi), n, dt, a0, a1, _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
     return out
+
+
+def mana_mixed(rho, *, ctx: Context | None = None, stream=None):
+    """[mana, Tr rho, Tr rho^2] of a mixed qutrit state given as a 3^n x 3^n GPU tensor (row-major,
+    complex64 or complex128)."""
+    torch = _torch()
+    ctx = ctx or default_context()
+    if not isinstance(rho, torch.Tensor) or not rho.is_cuda or rho.dim() != 2 or rho.shape[0] != rho.shape[1]:
+        raise TypeError("rho must be a square GPU tensor")
+    rho = rho.contiguous()
+    D = rho.shape[0]
+    n = round(math.log(D, 3)) if D > 0 else -1
+    if n < 1 or 3 ** n != D:
+        raise ValueError(f"dimension {D} is not 3^n with n >= 1")
+    dt = _dtype_code(rho)
+    out = torch.empty(3, dtype=torch.float64, device=rho.device)
+    ws = _workspace(workspace_size(OP_MANA_MIXED, n, dt, 1, 0, ctx), rho.device, stream)
+    _check(lib().hm_mana_mixed(ctx.h, _ptr(rho), n, dt, _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
+    return out
+
+
+def reduced_density_matrix(psi, n_a: int, *, ctx: Context | None = None, stream=None):
+    """Reduced density matrix (3^n_a x 3^n_a GPU tensor, the state's dtype) of a qutrit state on its
+    first n_a qutrits."""
+    torch = _torch()
+    ctx = ctx or default_context()
+    psi, n = _state(psi, 3)
+    dt = _dtype_code(psi)
+    if not 1 <= n_a <= min(n, 10):
+        raise ValueError(f"n_a = {n_a} outside [1, min(n, 10)]")
+    D = 3 ** n_a
+    rho = torch.empty((D, D), dtype=psi.dtype, device=psi.device)
+    _check(lib().hm_reduced_density(ctx.h, _ptr(psi), n, int(n_a), dt, _ptr(rho), _stream(stream)))
+    return rho

@@ -246,6 +246,9 @@ hm_status hm_workspace_size(hm_handle h, hm_op op, int n, hm_dtype dtype, int n_
       *bytes = align256((size_t)(count + 1) * 2 * sizeof(double)) + sre_workspace(p, 1, 0);
       return HM_OK;
     }
+    case HM_OP_MANA_MIXED:
+      HM_TRY(mixed_workspace(n, dbl, bytes));
+      return HM_OK;
     case HM_OP_MANA: {
       if (n < 1 || n > 16) return (hm_status)fail(E_SIZE, "mana: n = %d outside [1, 16]", n);
       int64_t mb;
@@ -676,6 +679,31 @@ hm_status hm_mana(hm_handle h, const void *psi, int n, hm_dtype dtype, double *o
   HM_TRY(check_ws(ws, ws_bytes, need));
   HM_TRY(norm_ok(h, psi, 3, n, dtype, stream));
   return (hm_status)mana_launch(n, dtype == HM_C128, mb, ms, psi, 0, D, nullptr, out, ws, ws_bytes, stream);
+}
+
+hm_status hm_mana_mixed(hm_handle h, const void *rho, int n, hm_dtype dtype, double *out, void *ws, size_t ws_bytes,
+                        hipStream_t stream) {
+  g_err[0] = 0;
+  if (!h) return (hm_status)fail(E_ARG, "h is NULL");
+  HM_TRY(check_dtype(dtype));
+  size_t need = 0;
+  HM_TRY(mixed_workspace(n, dtype == HM_C128, &need));
+  HM_TRY(check_ptr(rho, psi_align(dtype), "rho"));
+  HM_TRY(check_ptr(out, 8, "out"));
+  HM_TRY(check_ws(ws, ws_bytes, need));
+  return (hm_status)mixed_launch(n, dtype == HM_C128, rho, out, ws, stream);
+}
+
+hm_status hm_reduced_density(hm_handle h, const void *psi, int n, int n_a, hm_dtype dtype, void *rho,
+                             hipStream_t stream) {
+  g_err[0] = 0;
+  if (!h) return (hm_status)fail(E_ARG, "h is NULL");
+  HM_TRY(check_dtype(dtype));
+  if (n < 1 || n > 16) return (hm_status)fail(E_SIZE, "reduced density: n = %d outside [1, 16]", n);
+  if (n_a < 1 || n_a > n || n_a > 10) return (hm_status)fail(E_SIZE, "reduced density: n_a = %d outside [1, min(n, 10)]", n_a);
+  HM_TRY(check_ptr(psi, psi_align(dtype), "psi"));
+  HM_TRY(check_ptr(rho, psi_align(dtype), "rho"));
+  return (hm_status)reduced_density_launch(n, n_a, dtype == HM_C128, psi, rho, stream);
 }
 
 hm_status hm_mana_partial(hm_handle h, const void *psi, int n, hm_dtype dtype, uint64_t a0, uint64_t a1, double *sums,

@@ -356,3 +356,17 @@ def test_autotune_other_plans_argument_errors(L, h):
     assert L.hm_autotune_batched(hh, ps, ns, 1, 0, good, ws, 1 << 30, None) == HM_E_ARG
     assert L.hm_set_option(hh, 10, 3) == HM_E_ARG
     L.hm_destroy(hh)
+
+
+def test_mixed_and_reduced_density_argument_errors(L, h):
+    good, ws = P(0x100000), P(0x200000)
+    b = ctypes.c_size_t(0)
+    assert L.hm_workspace_size(h, 7, 8, 1, 1, 0, ctypes.byref(b)) == HM_OK
+    assert b.value >= 9 ** 8 * 16
+    assert L.hm_workspace_size(h, 7, 11, 0, 1, 0, ctypes.byref(b)) == HM_E_SIZE
+    assert L.hm_mana_mixed(h, good, 0, 0, good, ws, 1 << 40, None) == HM_E_SIZE
+    assert L.hm_mana_mixed(h, None, 4, 0, good, ws, 1 << 40, None) == HM_E_ARG
+    assert L.hm_mana_mixed(h, good, 4, 0, good, ws, 64, None) == HM_E_WORKSPACE
+    assert L.hm_reduced_density(h, good, 8, 9, 0, good, None) == HM_E_SIZE
+    assert L.hm_reduced_density(h, good, 12, 11, 0, good, None) == HM_E_SIZE
+    assert L.hm_reduced_density(h, good, 8, 4, 0, None, None) == HM_E_ARG
