@@ -311,6 +311,19 @@ def secondary(hm, S, torch, dev, psi, N):
                                              "ms": dt * 1e3, "value": 17 * 4 * (steps + 1) * 2.0 ** nm / dt,
                                              "unit": "Pauli expectations/s"}
             del v
+        # mixed-state mana of subsystems of a qutrit brick-wall state (depth 3), complex128 as in the
+        # paper's table: N_A = 8 of N = 10 and N_A = 10 of N = 11 (reduced density matrix included)
+        for nq, na in ((10, 8), (11, 10)):
+            x = torch.from_numpy(S.brickwall_haar(nq, 3, seed=9800 + nq, d=3)).to(dev)
+            rho = hm.reduced_density_matrix(x, na)
+            torch.cuda.synchronize()
+            dt, o = _timed(torch, lambda: hm.mana_mixed(rho))
+            sec["mana_mixed_na%d_c128" % na] = {"ms": dt * 1e3, "mana": float(o[0].item()), "trace": float(o[1].item()),
+                                                "purity": float(o[2].item()), "value": 9.0 ** na / dt,
+                                                "unit": "phase-space points/s",
+                                                "hbm_bytes": (2 * na + 1) * 9.0 ** na * 16,
+                                                "hbm_frac": (2 * na + 1) * 9.0 ** na * 16 / dt / 1e9 / HBM_PEAK_GBS}
+            del rho
     except hm.HmError as e:
         sec["error"] = str(e)[:200]
     return sec
