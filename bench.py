@@ -385,6 +385,12 @@ def main():
                     help="time only the fused forward + adjoint of M_2 at N qubits (profiling runs)")
     ap.add_argument("--mana-only", type=int, default=0, metavar="N",
                     help="profiling runs: time only the qutrit mana of an N-qutrit complex64 state per step")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="profiling runs: time only hm_sre_batched on the 1024 states with n in [10, 16] per step")
+    ap.add_argument("--mixed-only", type=int, default=0, metavar="NA",
+                    help="profiling runs: time only the mixed-state mana of an N_A-qutrit reduced density matrix")
+    ap.add_argument("--mc-only", type=int, default=0, metavar="N",
+                    help="profiling runs: time only the thermodynamic-integration Monte Carlo M_2 at N qubits")
     ap.add_argument("--oracle-table", action="store_true",
                     help="print GPU and oracle rates side by side for SRE n = 8, 12, 16, 20 and mana n = 6, 8, 10, 12"
                          " (oracle on a bounded prefix of the shifts) and exit")
@@ -423,6 +429,46 @@ def main():
                           "unit": "phase-space points/s", "ms_per_step": ms, "steps": args.steps,
                           "config": {"workload": f"mana, N={n} qutrits, complex64 Gaussian state, seed 1212"},
                           "mana": float(o[0].item())}), flush=True)
+        return
+    def only_loop(fn, name, unit, work, workload, extra=None):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            o = fn()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        rec = {"metric": name, "value": work / (ms * 1e-3), "unit": unit, "ms_per_step": ms, "steps": args.steps,
+               "config": {"workload": workload}}
+        rec.update(extra(o) if extra else {})
+        print(json.dumps(rec), flush=True)
+
+    if args.batched_only:
+        rng = np.random.default_rng(5005)
+        ns = rng.integers(10, 17, size=1024)
+        states = [torch.from_numpy(S.to_c64_exact(S.gaussian_state(int(n), seed=5000 + i))[0]).to(dev)
+                  for i, n in enumerate(ns)]
+        only_loop(lambda: hm.sre_batched(states, (2.0,)), "Pauli expectations/s (batched M_2)", "Pauli expectations/s",
+                  float(np.sum(4.0 ** ns)), "1024 complex64 Gaussian states, n uniform in [10, 16] (seed 5005), one call")
+        return
+    if args.mixed_only:
+        na = args.mixed_only
+        x = torch.from_numpy(S.brickwall_haar(na + 2, 3, seed=9800 + na + 2, d=3)).to(dev)
+        rho = hm.reduced_density_matrix(x, na)
+        only_loop(lambda: hm.mana_mixed(rho), "phase-space points/s (mixed-state mana)", "phase-space points/s",
+                  9.0 ** na, f"mixed-state mana, N_A={na} of a {na + 2}-qutrit brick-wall state (depth 3), complex128",
+                  lambda o: {"mana": float(o[0].item())})
+        return
+    if args.mc_only:
+        nm = args.mc_only
+        g = torch.Generator(device="cpu").manual_seed(2400 + nm)
+        v = torch.view_as_complex(torch.randn(2 ** nm, 2, generator=g, dtype=torch.float32)).to(dev)
+        v /= torch.linalg.vector_norm(v)
+        only_loop(lambda: hm.sre_mc(v, 17, 4, 200, 25, seed=9700 + nm)[0],
+                  "Pauli expectations/s (thermodynamic-integration M_2)", "Pauli expectations/s",
+                  17 * 4 * 201 * 2.0 ** nm, f"MC-TI M_2, N={nm}, complex64 Gaussian state, 17 beta x 4 chains x 200 steps",
+                  lambda o: {"M2_hat": float(o[0].item()), "dM2": float(o[1].item())})
         return
     if args.grad_only:
         n = args.grad_only
