@@ -1,4 +1,4 @@
-"""Seeded synthetic state vectors of N qudits (d = 2 qubits, d = 3 qutrits).
+"""Seeded synthetic state vectors of N qudits (d = 2 qubits, d = 3 qutrits, odd primes d = 5, 7).
 
 Conventions used everywhere in this repository:
 
@@ -26,7 +26,8 @@ __all__ = [
     "random_clifford_state", "clifford_t_state", "t_plus_clifford_state", "F3", "D3", "SUM3",
     "random_qutrit_clifford_ops", "random_qutrit_clifford_state", "ry_rz_cz_state",
     "ry_rz_cz_state_torch", "uniform_rows", "parity_conserving_state", "to_c64_exact",
-    "random_density", "pure_density", "ops_unitary",
+    "random_density", "pure_density", "ops_unitary", "qudit_clifford_gates", "random_qudit_clifford_ops",
+    "random_qudit_clifford_state", "qudit_cubic_phase",
 ]
 
 
@@ -236,6 +237,55 @@ def random_qutrit_clifford_ops(n: int, layers: int, seed: int) -> list:
 
 def random_qutrit_clifford_state(n: int, seed: int, layers: int | None = None) -> np.ndarray:
     return apply_ops(zero_state(n, 3), n, random_qutrit_clifford_ops(n, layers or 4 * n, seed), d=3)
+
+
+# ----------------------------------------------------------------------------------------------
+# Clifford circuits of qudits of odd prime dimension d
+# ----------------------------------------------------------------------------------------------
+def qudit_clifford_gates(d: int) -> dict:
+    """Generators of the single-qudit Clifford group for odd prime d and the two-qudit SUM gate:
+    F|j> = d^{-1/2} sum_k omega^{jk}|k>, P = diag(omega^{j^2}), X, Z; SUM|i, j> = |i, i + j>
+    (row/column index d*x_{k1} + x_{k2}, the layout of apply_2q)."""
+    w = np.exp(2j * math.pi / d)
+    j = np.arange(d)
+    F = w ** np.outer(j, j) / math.sqrt(d)
+    P = np.diag(w ** ((j * j) % d))
+    X = np.roll(np.eye(d), 1, axis=0).astype(np.complex128)
+    Z = np.diag(w ** j)
+    SUM = np.zeros((d * d, d * d), dtype=np.complex128)
+    for a in range(d):
+        for b in range(d):
+            SUM[d * a + (a + b) % d, d * a + b] = 1.0
+    return {"F": F.astype(np.complex128), "P": P.astype(np.complex128), "X": X, "Z": Z.astype(np.complex128),
+            "FP": (F @ P).astype(np.complex128), "PF": (P @ F).astype(np.complex128), "SUM": SUM}
+
+
+def qudit_cubic_phase(d: int, c: int = 1) -> np.ndarray:
+    """diag(omega^{c j^3}): a non-Clifford single-qudit gate for d >= 5 (a source of magic)."""
+    w = np.exp(2j * math.pi / d)
+    j = np.arange(d)
+    return np.diag(w ** ((c * j ** 3) % d)).astype(np.complex128)
+
+
+def random_qudit_clifford_ops(n: int, d: int, layers: int, seed: int) -> list:
+    """``layers`` layers of random single-qudit Clifford generators, then SUM on random disjoint pairs."""
+    gates = qudit_clifford_gates(d)
+    names = ["F", "P", "X", "Z", "FP", "PF"]
+    g = rng(seed)
+    ops = []
+    for _ in range(layers):
+        for k in range(n):
+            ops.append(("1q", k, gates[names[g.integers(len(names))]]))
+        perm = g.permutation(n)
+        for p in range(0, n - 1, 2):
+            if g.random() < 0.75:
+                ops.append(("2q", int(perm[p]), int(perm[p + 1]), gates["SUM"]))
+    return ops
+
+
+def random_qudit_clifford_state(n: int, d: int, seed: int, layers: int | None = None) -> np.ndarray:
+    """Stabilizer state of N qudits: a random Clifford circuit (4N layers by default) on |0...0>."""
+    return apply_ops(zero_state(n, d), n, random_qudit_clifford_ops(n, d, layers or 4 * n, seed), d=d)
 
 
 # ----------------------------------------------------------------------------------------------
