@@ -167,7 +167,8 @@ typedef enum {
   HM_OP_MANA = 4,       /* hm_mana and hm_mana_partial (count ignored)                       */
   HM_OP_SRE_SAMPLED = 5, /* hm_sre_sampled; count = n_rows                                   */
   HM_OP_SRE_GRAD_BATCHED = 6, /* hm_sre_grad_batched; count = batch                         */
-  HM_OP_MANA_MIXED = 7   /* hm_mana_mixed (count ignored)                                     */
+  HM_OP_MANA_MIXED = 7,  /* hm_mana_mixed (count ignored)                                     */
+  HM_OP_MANA_QUDIT = 8   /* hm_mana_qudit; count = d (3, 5 or 7)                              */
 } hm_op;
 hm_status hm_workspace_size(hm_handle h, hm_op op, int n, hm_dtype dtype, int n_q, int64_t count,
                             size_t *bytes);
@@ -180,7 +181,9 @@ hm_status hm_workspace_size(hm_handle h, hm_op op, int n, hm_dtype dtype, int n_
 hm_status hm_sre(hm_handle h, const void *psi, int n, hm_dtype dtype, const double *q, int n_q,
                  double *out, void *ws, size_t ws_bytes, hipStream_t stream);
 
-/* Raw sums over the X-shifts a in [a0, a1) (sharding, checkpoint/resume):
+/* Raw sums over the X-shifts a in [a0, a1): the X-string loop of Algorithm 2 cut into chunks
+ * (Sec. "Calculation of SRE for qubits": the loop over X-strings of Algorithm 2 splits into chunks
+ * evaluated independently), for sharding over devices and checkpoint/resume:
  *   sums[0] = sum_{a,b} |chi_b(a)|^2,
  *   sums[1+i] = sum_{a,b} |chi_b(a)|^{2 q_i}   (q_i == 1: sum |chi|^2 log2 |chi|^2).
  * Sums over disjoint ranges add up to the sums over their union.  0 <= a0 <= a1 <= 2^n.
@@ -215,7 +218,11 @@ hm_status hm_sre_row_values(hm_handle h, const void *psi, int n, hm_dtype dtype,
  * w_b(a) = |chi_b(a)|^{2q-2} chi_b(a), dS_q/dpsi*_y = 2q sum_a psi_{y XOR a} [H^{(x)n} w(a)]_y.
  * 1 <= n <= 20: one workgroup per X-shift up to n = 13 (HM_C64) / 12 (HM_C128), two-pass kernels
  * above (and for n >= 12 when HM_OPT_FORCE_PATH is 2).  The transforms of each shift are recomputed
- * (nothing is stored across shifts); the gradient accumulates in FP64. */
+ * (nothing is stored across shifts).  Precision of the accumulation over shifts: the scalar sums
+ * are FP64; the gradient is summed in the state's precision within a workgroup (the resident
+ * kernels hold one copy of it per workgroup in LDS, i.e. FP32 for HM_C64, over the shifts that
+ * workgroup takes) and in FP64 across workgroups; the two-pass kernels add every batch of shifts
+ * into FP64 partials. */
 hm_status hm_sre_grad(hm_handle h, const void *psi, int n, hm_dtype dtype, double q, double *out,
                       void *grad, void *ws, size_t ws_bytes, hipStream_t stream);
 
@@ -231,8 +238,8 @@ hm_status hm_sre_grad_batched(hm_handle h, const void *const *psis, int n, int b
                               hipStream_t stream);
 
 /* Many states, each of its own qubit count, in one call (all of one dtype and one q list): the
- * batched form of Algorithm 2 (every X-shift of every state is an independent transform, the
- * paper's chunking of the X-string loop).
+ * batched form of Algorithm 2 (every X-shift of every state is an independent transform; the
+ * chunks of the X-string loop that Sec. "Calculation of SRE for qubits" evaluates separately).
  * psis: HOST array of `batch` DEVICE pointers (one state each); ns: HOST array of their n.
  * out: device, batch * (n_q + 1) doubles; out[s*(n_q+1) + i] = M_{q_i}(psi_s), out[s*(n_q+1) + n_q]
  * = lost_norm of state s (as hm_sre).  The states whose folded vector fits one workgroup tile
@@ -251,8 +258,9 @@ hm_status hm_sre_batched(hm_handle h, const void *const *psis, const int *ns, in
                          const double *q, int n_q, double *out, void *ws, size_t ws_bytes,
                          hipStream_t stream);
 
-/* Monte Carlo estimate of M_2 from sampled X-rows (Sec. on sampling the Pauli spectrum; a row is
- * one transform, Eq. feP).  S(a) = sum_b |chi_b(a)|^4 and M_2 = -log2(mean over all a of S(a)).  The
+/* Monte Carlo estimate of M_2 from sampled X-rows (Sec. "Monte Carlo sampling algorithm for SRE":
+ * a row is one transform, Eq. feP; here with uniform rows instead of the Metropolis chain of
+ * hm_sre_mc).  S(a) = sum_b |chi_b(a)|^4 and M_2 = -log2(mean over all a of S(a)).  The
  * row a = 0 holds the identity, whose single term <I>^4 = 1 is about a quarter of the sum for
  * Haar-like states and would almost never be drawn, so that row is always evaluated exactly and the sampled rows
  * (caller-drawn, e.g. i.i.d. uniform in [1, 2^n); entries equal to 0 are skipped) estimate the
@@ -325,15 +333,40 @@ hm_status hm_sre_noalloc(hm_handle h, const void *psi, int n, hm_dtype dtype, co
 /* ------------------------------------------------------------------------------------------ */
 /* out[0] = mana = log2(sum_u |<psi|A_u|psi>| / 3^n); out[1] = sum_u W(u) (= 1);
  * out[2] = 3^n sum_u W(u)^2 (= 1 for a normalised pure state).  1 <= n <= 16.
- * out: device, 3 doubles. */
+ * out: device, 3 doubles.
+ * Error of HM_C64 (FP32 transforms): every value chi_b(a) carries rounding noise of order 1e-7 of
+ * the largest |chi|; where chi is exactly zero, |.| turns that noise into a one-sided excess of
+ * sum |chi|, so the FP32 mana lies ABOVE the exact one by up to about 1.5e-5 at n = 10 and 4.5e-5
+ * at n = 12 for states whose phase-space spectrum is mostly exact zeros (stabilizer states,
+ * measured on MI355X), growing by about sqrt(3) per qutrit (about 4e-4 at n = 16).  States with
+ * few exact zeros (Haar-like states) are within 1e-5 of the exact mana for n <= 12.  HM_C128 agrees
+ * with the FP64 definition to about 1e-12 relative. */
 hm_status hm_mana(hm_handle h, const void *psi, int n, hm_dtype dtype, double *out, void *ws,
                   size_t ws_bytes, hipStream_t stream);
 
-/* Raw sums over shifts a in [a0, a1) (a = sum_k a_k 3^k): sums = {sum |chi|, sum chi, sum chi^2}.
+/* Raw sums over shifts a in [a0, a1) (a = sum_k a_k 3^k), the shift loop of Algorithm 4 cut into
+ * chunks as the X-string loop of Algorithm 2 is (Sec. "Calculation of SRE for qubits"):
+ * sums = {sum |chi|, sum chi, sum chi^2}.
  * sums: device, 3 doubles (overwritten).  0 <= a0 <= a1 <= 3^n. */
 hm_status hm_mana_partial(hm_handle h, const void *psi, int n, hm_dtype dtype, uint64_t a0,
                           uint64_t a1, double *sums, void *ws, size_t ws_bytes, hipStream_t stream);
 
+
+/* Pure-state mana of n qudits of odd prime dimension d in {3, 5, 7}: the construction of Sec. "Mana
+ * for qutrits", which its footnote extends to every odd prime d (clock and shift operators with
+ * omega = exp(2 pi i / d), T_ab = omega^{-2^{-1} a b} Z^a X^b, phase-space point operators A_u,
+ * W(u) = <psi|A_u|psi> / d^n), computed by Algorithm 4 with radix-d transforms: for every shift a,
+ * v_x = conj(alpha_x) alpha_{-x} with alpha = X_a psi, chi(a) = F_d^{(x)n} v, (F_d)_{jk} = omega^{2jk}.
+ * psi: device, d^n amplitudes (qudit k = base-d digit k of the index), not renormalised.
+ * out: device, 3 doubles = {mana = log2(sum_u |<psi|A_u|psi>| / d^n), sum_u W(u), d^n sum_u W(u)^2}
+ * (1 and 1 for a normalised pure state).  The d^n values of a shift pair are transformed inside one
+ * workgroup's LDS, which bounds n: 1 <= n <= 9 / 6 / 5 for d = 3 / 5 / 7 (HM_C64) and 8 / 5 / 4
+ * (HM_C128); HM_E_SIZE above.  For d = 3, hm_mana is the fast path (to n = 16); this entry point
+ * computes the same value through the generic kernel.  Precision as hm_mana (FP32 transforms and
+ * FP64 sums for HM_C64).  Workspace: hm_workspace_size(HM_OP_MANA_QUDIT, count = d); HM_E_ARG for
+ * d not in {3, 5, 7}. */
+hm_status hm_mana_qudit(hm_handle h, const void *psi, int n, int d, hm_dtype dtype, double *out, void *ws,
+                        size_t ws_bytes, hipStream_t stream);
 
 /* Mana of a mixed state (Sec. "Mana of mixed states via a fast tensor-product transform", Eq.
  * MN_factor_mana and its Algorithm): all 9^n values w_u = Tr(rho A_u) as the tensor power of a 9 x 9

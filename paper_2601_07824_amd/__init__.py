@@ -18,7 +18,7 @@ from typing import Sequence
 
 __all__ = [
     "HmError", "lib", "lib_path", "Context", "default_context", "sre", "sre_partial", "sre_finalize",
-    "sre_rows", "sre_row_values", "sre_noalloc", "sre_mc", "McParams", "mc_random_inputs", "sre_grad", "sre_grad_batched", "SRE", "SREBatched", "sre_batched", "sre_sampled", "autotune", "autotune_mana", "autotune_grad", "autotune_batched", "tuned_plan", "mana", "mana_partial", "mana_mixed", "reduced_density_matrix", "workspace_size",
+    "sre_rows", "sre_row_values", "sre_noalloc", "sre_mc", "McParams", "mc_random_inputs", "sre_grad", "sre_grad_batched", "SRE", "SREBatched", "sre_batched", "sre_sampled", "autotune", "autotune_mana", "autotune_grad", "autotune_batched", "tuned_plan", "mana", "mana_partial", "mana_mixed", "mana_qudit", "reduced_density_matrix", "workspace_size",
     "HM_C64", "HM_C128", "profile_enable", "profile_reset", "profile_read", "OP_SRE", "OP_SRE_ROWS", "OP_ROW_VALUES", "OP_SRE_GRAD", "OP_MANA",
     "OP_SRE_SAMPLED", "OP_SRE_GRAD_BATCHED", "EXPORTED_SYMBOLS",
 ]
@@ -29,6 +29,7 @@ lib_path = os.path.join(_HERE, "libhmag.so")
 HM_C64, HM_C128 = 0, 1
 OP_SRE, OP_SRE_ROWS, OP_ROW_VALUES, OP_SRE_GRAD, OP_MANA, OP_SRE_SAMPLED, OP_SRE_GRAD_BATCHED = 0, 1, 2, 3, 4, 5, 6
 OP_MANA_MIXED = 7
+OP_MANA_QUDIT = 8
 OPT_FORCE_PATH, OPT_BATCH_SHIFTS, OPT_ROW_RB, OPT_COL_RB, OPT_ROW_BITS, OPT_PIPELINE, OPT_LDS_SPLIT, OPT_STREAMS = \
     1, 2, 3, 4, 5, 6, 7, 8
 OPT_CHECK_NORM = 9
@@ -61,6 +62,7 @@ _SIGS = {
     "hm_mana": (_i, [_vp, _vp, _i, _i, _vp, _vp, _sz, _vp]),
     "hm_mana_partial": (_i, [_vp, _vp, _i, _i, _u64, _u64, _vp, _vp, _sz, _vp]),
     "hm_mana_mixed": (_i, [_vp, _vp, _i, _i, _vp, _vp, _sz, _vp]),
+    "hm_mana_qudit": (_i, [_vp, _vp, _i, _i, _i, _vp, _vp, _sz, _vp]),
     "hm_reduced_density": (_i, [_vp, _vp, _i, _i, _i, _vp, _vp]),
     "hm_sre_batched_workspace": (_i, [_vp, ctypes.POINTER(_i), _i, _i, _i, ctypes.POINTER(_sz)]),
     "hm_sre_batched": (_i, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_i), _i, _i, _dp, _i, _vp, _vp, _sz, _vp]),
@@ -667,6 +669,21 @@ def mana_mixed(rho, *, ctx: Context | None = None, stream=None):
     out = torch.empty(3, dtype=torch.float64, device=rho.device)
     ws = _workspace(workspace_size(OP_MANA_MIXED, n, dt, 1, 0, ctx), rho.device, stream)
     _check(lib().hm_mana_mixed(ctx.h, _ptr(rho), n, dt, _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
+    return out
+
+
+def mana_qudit(psi, d: int, *, ctx: Context | None = None, stream=None):
+    """[mana, sum W, d^n sum W^2] of a pure state of n qudits of odd prime dimension d in {3, 5, 7}
+    (GPU tensor of d^n amplitudes, complex64 or complex128)."""
+    torch = _torch()
+    ctx = ctx or default_context()
+    if d not in (3, 5, 7):
+        raise ValueError(f"d = {d} is not 3, 5 or 7")
+    psi, n = _state(psi, d)
+    dt = _dtype_code(psi)
+    out = torch.empty(3, dtype=torch.float64, device=psi.device)
+    ws = _workspace(workspace_size(OP_MANA_QUDIT, n, dt, 1, d, ctx), psi.device, stream)
+    _check(lib().hm_mana_qudit(ctx.h, _ptr(psi), n, int(d), dt, _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
     return out
 
 

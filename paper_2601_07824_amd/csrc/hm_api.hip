@@ -249,6 +249,11 @@ hm_status hm_workspace_size(hm_handle h, hm_op op, int n, hm_dtype dtype, int n_
     case HM_OP_MANA_MIXED:
       HM_TRY(mixed_workspace(n, dbl, bytes));
       return HM_OK;
+    case HM_OP_MANA_QUDIT:
+      if (count != 3 && count != 5 && count != 7)
+        return (hm_status)fail(E_ARG, "qudit mana: count (d) = %lld is not 3, 5 or 7", (long long)count);
+      HM_TRY(qudit_workspace(n, (int)count, dbl, bytes));
+      return HM_OK;
     case HM_OP_MANA: {
       if (n < 1 || n > 16) return (hm_status)fail(E_SIZE, "mana: n = %d outside [1, 16]", n);
       int64_t mb;
@@ -692,6 +697,19 @@ hm_status hm_mana_mixed(hm_handle h, const void *rho, int n, hm_dtype dtype, dou
   HM_TRY(check_ptr(out, 8, "out"));
   HM_TRY(check_ws(ws, ws_bytes, need));
   return (hm_status)mixed_launch(n, dtype == HM_C128, rho, out, ws, stream);
+}
+
+hm_status hm_mana_qudit(hm_handle h, const void *psi, int n, int d, hm_dtype dtype, double *out, void *ws,
+                        size_t ws_bytes, hipStream_t stream) {
+  g_err[0] = 0;
+  if (!h) return (hm_status)fail(E_ARG, "h is NULL");
+  HM_TRY(check_dtype(dtype));
+  size_t need = 0;
+  HM_TRY(qudit_workspace(n, d, dtype == HM_C128, &need));
+  HM_TRY(check_ptr(psi, psi_align(dtype), "psi"));
+  HM_TRY(check_ptr(out, 8, "out"));
+  HM_TRY(check_ws(ws, ws_bytes, need));
+  return (hm_status)qudit_launch(n, d, dtype == HM_C128, psi, out, ws, stream);
 }
 
 hm_status hm_reduced_density(hm_handle h, const void *psi, int n, int n_a, hm_dtype dtype, void *rho,

@@ -221,6 +221,11 @@ size_t sre_grad2_workspace_f64(const SrePlan &p);
 // streams: two-pass batches alternate over 1 or 2 streams (0 = automatic, HM_OPT_STREAMS).
 int mana_launch(int N, int dbl, int64_t batch, int streams, const void *psi, uint64_t a0, uint64_t a1, double *sums,
                 double *out, void *ws, size_t ws_bytes, hipStream_t stream);
+// Pure-state mana of qudits of odd prime dimension d in {3, 5, 7} (hm_qudit.hip): out = {mana, sum W,
+// d^N sum W^2}; the d^N-value transform of a shift pair lives in one workgroup's LDS.
+int qudit_nmax_of(int d, int dbl);
+int qudit_workspace(int N, int d, int dbl, size_t *bytes);
+int qudit_launch(int N, int d, int dbl, const void *psi, double *out, void *ws, hipStream_t st);
 // Mixed-state mana (hm_mixed.hip): rho row-major 3^N x 3^N; out = {mana, Tr rho, Tr rho^2}.
 int mixed_workspace(int N, int dbl, size_t *bytes);
 int mixed_launch(int N, int dbl, const void *rho, double *out, void *ws, hipStream_t st);

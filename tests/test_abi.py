@@ -370,3 +370,22 @@ def test_mixed_and_reduced_density_argument_errors(L, h):
     assert L.hm_reduced_density(h, good, 8, 9, 0, good, None) == HM_E_SIZE
     assert L.hm_reduced_density(h, good, 12, 11, 0, good, None) == HM_E_SIZE
     assert L.hm_reduced_density(h, good, 8, 4, 0, None, None) == HM_E_ARG
+
+
+def test_qudit_mana_argument_errors(L, h):
+    good, ws = P(0x100000), P(0x200000)
+    b = ctypes.c_size_t(0)
+    for d, nmax64, nmax128 in ((3, 9, 8), (5, 6, 5), (7, 5, 4)):
+        assert L.hm_workspace_size(h, 8, nmax64, 0, 1, d, ctypes.byref(b)) == HM_OK
+        assert b.value >= 3 * 8
+        assert L.hm_workspace_size(h, 8, nmax64 + 1, 0, 1, d, ctypes.byref(b)) == HM_E_SIZE
+        assert L.hm_workspace_size(h, 8, nmax128, 1, 1, d, ctypes.byref(b)) == HM_OK
+        assert L.hm_workspace_size(h, 8, nmax128 + 1, 1, 1, d, ctypes.byref(b)) == HM_E_SIZE
+        assert L.hm_mana_qudit(h, good, nmax64 + 1, d, 0, good, ws, 1 << 30, None) == HM_E_SIZE
+    assert L.hm_workspace_size(h, 8, 3, 0, 1, 4, ctypes.byref(b)) == HM_E_ARG
+    assert L.hm_mana_qudit(h, good, 3, 4, 0, good, ws, 1 << 30, None) == HM_E_ARG
+    assert L.hm_mana_qudit(h, good, 0, 5, 0, good, ws, 1 << 30, None) == HM_E_SIZE
+    assert L.hm_mana_qudit(h, None, 3, 5, 0, good, ws, 1 << 30, None) == HM_E_ARG
+    assert L.hm_mana_qudit(h, good, 3, 5, 0, None, ws, 1 << 30, None) == HM_E_ARG
+    assert L.hm_mana_qudit(h, good, 3, 5, 0, good, ws, 8, None) == HM_E_WORKSPACE
+    assert L.hm_mana_qudit(h, good, 3, 5, 2, good, ws, 1 << 30, None) == HM_E_DTYPE
