@@ -207,6 +207,9 @@ def secondary(hm, S, torch, dev, psi, N):
     try:
         x128 = torch.from_numpy(psi).to(dev)
         c128 = hm.Context()
+        # one stream, as the headline: with two, a kernel's event-bracketed time overlaps the other
+        # stream's kernels and no longer measures that kernel
+        c128.set_option(hm.OPT_STREAMS, 1)
         hm.autotune(x128, 16384, ctx=c128)
         dt, o, prof = profiled(hm, torch, lambda: hm.sre(x128, (2.0,), ctx=c128), every=64)
         m2 = float(o[0].item())

@@ -15,7 +15,7 @@ the thermodynamic-integration scheme and its Algorithm), in its notation:
   * error bar  dM_2 = (1/ln 2) sqrt( sum_l w_l^2 2 tau_l sigma_l^2 / n_l ) (Eqs. Var_I_eps, m2error),
     tau_l the integrated autocorrelation time of the chain at beta_l.
 
-Readings taken where the paper is silent or inconsistent (listed in the design doc as well):
+Readings taken where the paper is silent or inconsistent:
   * sign of the integration identity: Eq. TI_logZ_reg states ln Z_1 - ln Z_0, the negative of what
     Eq. f_expect_beta_reg integrates to, and the algorithm's return value -I / ln 2 is then negative
     for every state with S(a) < 1; the reading I = ln Z_0 - ln Z_1, M_2 = -log2(e^-I - eps) (= I / ln 2
