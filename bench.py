@@ -327,6 +327,16 @@ def secondary(hm, S, torch, dev, psi, N):
                                                 "hbm_bytes": (2 * na + 1) * 9.0 ** na * 16,
                                                 "hbm_frac": (2 * na + 1) * 9.0 ** na * 16 / dt / 1e9 / HBM_PEAK_GBS}
             del rho
+        # pure-state mana of qudits of odd prime dimension at the largest sizes of the LDS-resident
+        # kernel (Gaussian states): d^(2n) phase-space points per evaluation
+        for d, nd, dt_ in ((5, 6, torch.complex64), (7, 5, torch.complex64), (5, 5, torch.complex128),
+                           (7, 4, torch.complex128)):
+            x = torch.from_numpy(S.gaussian_state(nd, d, seed=9900 + 10 * d + nd)).to(dt_).to(dev)
+            dt, o = _timed(torch, lambda: hm.mana_qudit(x, d))
+            sec["mana_qudit_d%d_n%d_%s" % (d, nd, "c64" if dt_ == torch.complex64 else "c128")] = {
+                "ms": dt * 1e3, "mana": float(o[0].item()), "value": float(d) ** (2 * nd) / dt,
+                "unit": "phase-space points/s"}
+            del x
     except hm.HmError as e:
         sec["error"] = str(e)[:200]
     return sec
