@@ -74,8 +74,10 @@ const char *hm_version(void);
  *   HM_OPT_BATCH_SHIFTS: X-shifts covered by one two-pass launch pair (qubit SRE and qutrit mana).
  *   HM_OPT_ROW_RB / HM_OPT_COL_RB: log2 of the values each thread holds in registers in the
  *     two-pass row / column kernels (4 or 5 for HM_C64, 4 for HM_C128).
- *   HM_OPT_ROW_BITS: index bits handled by the two-pass row pass (6..13); the column pass takes
- *     the remaining n - 1 - row_bits.
+ *   HM_OPT_ROW_BITS: index bits handled by the two-pass row pass (6..13; 14 and 15 for HM_C64); the
+ *     column pass takes the remaining n - 1 - row_bits.  Unset, the row pass takes about half the
+ *     bits, and from n = 22 on (HM_C64, sequential launches) 13, 14 at n = 25 and 15 at n = 26, so
+ *     that the column tiles keep reading several contiguous values of each row.
  *   HM_OPT_PIPELINE: two-pass launches, 1 = one row pass then one column pass per batch of
  *     shifts, 2 = pipelined (each launch runs the row pass of batch k beside the column pass of
  *     batch k - 1, with two exchange buffers; default tiles and split only).
@@ -120,7 +122,8 @@ hm_status hm_set_option(hm_handle h, hm_option opt, int64_t value);
 /* Autotuner.  Times every candidate SRE plan for (n, dtype) on the state psi (device) over the
  * first sample_shifts X-shifts (16384 if <= 0, at most 2^n): the workgroup-resident kernel where it
  * applies, and two-pass plans over exchange batches of 64/128/256 MiB, both LDS stagings,
- * sequential launches (one or two streams) with the default, 11, 12 or 13 row bits, and pipelined
+ * sequential launches (one or two streams) with the default, 11, 12 or 13 row bits (and 14, 15 for
+ * HM_C64 from n = 20 on), and pipelined
  * launches.  Options already set on the handle are kept fixed.  The fastest plan is stored in the handle; later calls
  * on the handle for the same (n, dtype) fill every option left automatic from it.  Candidates
  * whose workspace exceeds ws_bytes are skipped (hm_autotune_workspace gives the size that admits

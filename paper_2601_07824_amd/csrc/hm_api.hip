@@ -178,7 +178,7 @@ hm_status hm_set_option(hm_handle h, hm_option opt, int64_t value) {
       h->opts.col_rb = (int)value;
       return HM_OK;
     case HM_OPT_ROW_BITS:
-      if (value != 0 && (value < 6 || value > 13)) return (hm_status)fail(E_ARG, "HM_OPT_ROW_BITS %lld not in {0, 6..13}", (long long)value);
+      if (value != 0 && (value < 6 || value > 15)) return (hm_status)fail(E_ARG, "HM_OPT_ROW_BITS %lld not in {0, 6..15}", (long long)value);
       h->opts.row_bits = (int)value;
       return HM_OK;
     case HM_OPT_PIPELINE:

@@ -23,8 +23,7 @@ __global__ __launch_bounds__(NT) void k_sre_colpass_adj(ColPassArgs A) {
   using Sh = ColShape<T, NT, RB, NH, CB, SPLIT>;
   __shared__ typename Sh::Elem lds[Sh::LDS_N];
   __shared__ double red[NT / 64 + 1];
-  for (int64_t s = (int64_t)blockIdx.x * NT + threadIdx.x; s < A.prev_n_slots; s += (int64_t)gridDim.x * NT)
-    reduce_shift(A.prev_partials, s, A.n_cb, A.nacc, A.prev_a0, A.prev_rows, A.nf, A.qa, A.prev_shift_sums);
+  reduce_prev_shifts(A, (int64_t)blockIdx.x * (NT / 64), (int64_t)gridDim.x * (NT / 64));
   colpass_tiles<T, NT, RB, NH, CB, QM, SPLIT, true, true>(A, blockIdx.x, gridDim.x, lds, red);
 }
 
@@ -534,8 +533,7 @@ int grad2_t(const SrePlan &p, const void *psi, double q, double *out, void *grad
     prev_nb = nb;
   }
   {
-    const int thr = 128;
-    hipLaunchKernelGGL(k_sre_shift_reduce, dim3((unsigned)((prev_nb + thr - 1) / thr)), dim3(thr), 0, st,
+    hipLaunchKernelGGL(k_sre_shift_reduce, dim3(shift_reduce_grid(prev_nb)), dim3(SHIFT_REDUCE_NT), 0, st,
                        partials[(k + 1) & 1], prev_nb, n_cb, nacc, (uint64_t)prev_s0, nullptr, nf, qa,
                        shift_sums + prev_s0 * nacc);
   }

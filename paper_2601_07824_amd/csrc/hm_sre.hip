@@ -219,8 +219,19 @@ int sre_plan(int N, int dbl, const PlanOpts &o, SrePlan *p) {
     if (dbl ? (row_rb != 4 || col_rb != 4) : ((row_rb != 4 && row_rb != 5) || (col_rb != 4 && col_rb != 5)))
       return fail(E_UNSUPPORTED, "SRE: register tiles (%d, %d) not built for this dtype", row_rb, col_rb);
     const int col_tb = sre_default_col_tb(P.nf, dbl, col_rb);
-    const int nl_max = 13, nl_min = 6;
+    // rows of up to 2^13 values; FP32 row tiles of 2^14 (2^4 or 2^5 values per thread) and 2^15
+    // (2^5 per thread) as well
+    const int nl_max = dbl ? 13 : (row_rb == 5 ? 15 : 14), nl_min = 6;
     int nl = o.row_bits ? o.row_bits : sre_default_nl(P.nf, col_tb, col_rb);
+    // From 2^21 folded values on, the default split leaves column tiles 2^1..2^3 columns wide, so a
+    // column read uses 16-64 contiguous bytes per row; longer rows widen them at the cost of a
+    // slower row pass.  Measured on MI355X (256 shifts): n = 22 best with 12-13 row bits, n = 24
+    // with 13 (13.9 ms against 14.7 for 12 and 15.9 for 15); the rows grow by one bit per qubit
+    // beyond that (2^15 at n = 26).  Pipelined kernels are built for the default split only.
+    if (!o.row_bits && !dbl && row_rb == 5 && P.nf >= 21 && o.pipeline != 2 && o.lds_split != 1) {
+      const int want = P.nf - 10 > 13 ? P.nf - 10 : 13;
+      nl = want < nl_max ? want : nl_max;
+    }
     int nh = P.nf - nl;
     if (nh < col_rb || nh > col_tb || nl < col_tb - nh || nl > nl_max || nl < nl_min)
       return fail(E_UNSUPPORTED, "SRE: no two-pass split for n = %d (row bits %d, column tile 2^%d)", N, nl, col_tb);
@@ -240,6 +251,8 @@ int sre_plan(int N, int dbl, const PlanOpts &o, SrePlan *p) {
     if (o.lds_split == 2 && !split_ok)
       return fail(E_UNSUPPORTED, "SRE: split LDS staging needs the default column register tiles (2^%d)", RB);
     P.split = split_ok && (o.lds_split == 2 || (o.lds_split == 0 && !dbl && SRE_SPLIT_DEFAULT));
+    if (nl == 15 && !P.split)
+      return fail(E_UNSUPPORTED, "SRE: rows of 2^15 values need split LDS staging (HM_OPT_LDS_SPLIT 0 or 2)");
     if (o.streams == 2 && P.pipe) return fail(E_UNSUPPORTED, "SRE: two streams apply to sequential launches only");
     P.streams = (o.streams == 2 || (o.streams == 0 && SRE_STREAMS_DEFAULT == 2 && !P.pipe)) ? 2 : 1;
     // Untuned batch: 256 MiB of exchange per FP32 launch (measured best at n = 20 on MI355X: the

@@ -235,18 +235,39 @@ struct ColPassArgs {
   uint64_t a0;  // shift of slot 0 (adjoint column pass only)
 };
 
-// Per-shift sum over column blocks (fixed order), unfolded and scaled.
-__device__ __forceinline__ void reduce_shift(const double *partials, int64_t slot, int64_t n_cb, int nacc, uint64_t a0,
-                                             const uint64_t *rows, int nf, const QArgs &qa, double *shift_sums) {
+// Per-shift sum over the column blocks, unfolded and scaled, by the 64 lanes of one wave (all of
+// them must call it): lane l adds blocks l, l + 64, ... in order, then a fixed shuffle tree adds the
+// lanes, so the result does not depend on timing.  (One thread per shift would walk 2^10 blocks per
+// shift serially at n = 24.)
+__device__ __forceinline__ void reduce_shift_wave(const double *partials, int64_t slot, int64_t n_cb, int nacc,
+                                                  uint64_t a0, const uint64_t *rows, int nf, const QArgs &qa,
+                                                  double *shift_sums, uint32_t lane) {
   double s[HM_MAX_Q + 1];
-  for (int k = 0; k < nacc; ++k) s[k] = 0.0;
+#pragma unroll
+  for (int k = 0; k < HM_MAX_Q + 1; ++k) s[k] = 0.0;
   const double *p = partials + slot * n_cb * nacc;
-  for (int64_t c = 0; c < n_cb; ++c)
-    for (int k = 0; k < nacc; ++k) s[k] += p[c * nacc + k];
-  const uint64_t a = rows ? rows[slot] : a0 + (uint64_t)slot;
-  const bool bad = (a >> (nf + 1)) != 0;
-  unfold_scale(s, nacc, qa, a == 0);
-  for (int k = 0; k < nacc; ++k) shift_sums[slot * nacc + k] = bad ? __builtin_nan("") : s[k];
+  for (int64_t c = lane; c < n_cb; c += 64)
+#pragma unroll
+    for (int k = 0; k < HM_MAX_Q + 1; ++k)
+      if (k < nacc) s[k] += p[c * nacc + k];
+#pragma unroll
+  for (int k = 0; k < HM_MAX_Q + 1; ++k)
+    if (k < nacc)
+      for (int off = 32; off > 0; off >>= 1) s[k] += __shfl_down(s[k], off, 64);
+  if (lane == 0) {
+    const uint64_t a = rows ? rows[slot] : a0 + (uint64_t)slot;
+    const bool bad = (a >> (nf + 1)) != 0;
+    unfold_scale(s, nacc, qa, a == 0);
+    for (int k = 0; k < nacc; ++k) shift_sums[slot * nacc + k] = bad ? __builtin_nan("") : s[k];
+  }
+}
+
+// Slots s0, s0 + step, ... < n of the previous batch, one wave each (wave w of the workgroup takes
+// the w-th of the workgroup's slots).
+__device__ __forceinline__ void reduce_prev_shifts(const ColPassArgs &C, int64_t first_wave, int64_t wave_step) {
+  const uint32_t lane = threadIdx.x & 63;
+  for (int64_t s = first_wave + (threadIdx.x >> 6); s < C.prev_n_slots; s += wave_step)
+    reduce_shift_wave(C.prev_partials, s, C.n_cb, C.nacc, C.prev_a0, C.prev_rows, C.nf, C.qa, C.prev_shift_sums, lane);
 }
 
 __host__ __device__ constexpr int cp_S(int NH, int RB, int CB, int k) {
@@ -377,16 +398,22 @@ __global__ __launch_bounds__(NT) void k_sre_colpass(ColPassArgs A) {
   using Sh = ColShape<T, NT, RB, NH, CB, SPLIT>;
   __shared__ typename Sh::Elem lds[Sh::LDS_N];
   __shared__ double red[NT / 64 + 1];
-  for (int64_t s = (int64_t)blockIdx.x * NT + threadIdx.x; s < A.prev_n_slots; s += (int64_t)gridDim.x * NT)
-    reduce_shift(A.prev_partials, s, A.n_cb, A.nacc, A.prev_a0, A.prev_rows, A.nf, A.qa, A.prev_shift_sums);
+  reduce_prev_shifts(A, (int64_t)blockIdx.x * (NT / 64), (int64_t)gridDim.x * (NT / 64));
   colpass_tiles<T, NT, RB, NH, CB, QM, SPLIT, false, true>(A, blockIdx.x, gridDim.x, lds, red);
 }
 
-// per-shift sums from column-pass partials of the last batch
-__global__ void k_sre_shift_reduce(const double *partials, int64_t n_slots, int64_t n_cb, int nacc, uint64_t a0,
-                                   const uint64_t *rows, int nf, QArgs qa, double *shift_sums) {
-  const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (slot < n_slots) reduce_shift(partials, slot, n_cb, nacc, a0, rows, nf, qa, shift_sums);
+// per-shift sums from column-pass partials of the last batch: one wave per shift (launch
+// SHIFT_REDUCE_NT threads per workgroup, ceil(n_slots / (SHIFT_REDUCE_NT / 64)) workgroups)
+constexpr int SHIFT_REDUCE_NT = 256;
+__global__ __launch_bounds__(SHIFT_REDUCE_NT) void k_sre_shift_reduce(const double *partials, int64_t n_slots,
+                                                                     int64_t n_cb, int nacc, uint64_t a0,
+                                                                     const uint64_t *rows, int nf, QArgs qa,
+                                                                     double *shift_sums) {
+  const int64_t slot = (int64_t)blockIdx.x * (SHIFT_REDUCE_NT / 64) + (threadIdx.x >> 6);
+  if (slot < n_slots) reduce_shift_wave(partials, slot, n_cb, nacc, a0, rows, nf, qa, shift_sums, threadIdx.x & 63);
+}
+static inline unsigned shift_reduce_grid(int64_t n_slots) {
+  return (unsigned)((n_slots + SHIFT_REDUCE_NT / 64 - 1) / (SHIFT_REDUCE_NT / 64));
 }
 
 
@@ -480,7 +507,7 @@ static int launch_resident(int NL, RowPassArgs A, bool q2, hipStream_t st, bool 
 // Two-pass row pass: rows of 2^NL values, tiles of 2^12 values (2^13 for NL = 13), RB register bits.
 template <typename T, int RB, bool SPLIT>
 static int launch_rowwrite_rb(int NL, RowPassArgs A, hipStream_t st) {
-  constexpr int NT12 = 1 << (12 - RB), NT13 = 1 << (13 - RB);
+  constexpr int NT12 = 1 << (12 - RB), NT13 = 1 << (13 - RB), NT14 = 1 << (14 - RB), NT15 = 1 << (15 - RB);
 #define HM_RW(nl, nt)                                               \
   case nl:                                                          \
     A.n_tiles = row_tiles<nt, RB, nl>(A);                           \
@@ -489,6 +516,22 @@ static int launch_rowwrite_rb(int NL, RowPassArgs A, hipStream_t st) {
   switch (NL) {
     HM_RW(6, NT12) HM_RW(7, NT12) HM_RW(8, NT12) HM_RW(9, NT12) HM_RW(10, NT12) HM_RW(11, NT12) HM_RW(12, NT12)
     HM_RW(13, NT13)
+    // rows of 2^14 / 2^15 values (workgroups of 512 / 1024 threads with 2^5-value FP32 tiles): the
+    // long rows that keep the column tiles wide from 2^21 folded values on
+    case 14:
+      if constexpr (sizeof(T) == 4 && NT14 <= 1024) {
+        A.n_tiles = row_tiles<NT14, RB, 14>(A);
+        launch_row_q<T, NT14, RB, 14, true, SPLIT>(A, false, st);
+        return OK;
+      }
+      break;
+    case 15:  // split staging only: whole-complex staging needs more registers than 1024 threads have
+      if constexpr (sizeof(T) == 4 && NT15 <= 1024 && SPLIT) {
+        A.n_tiles = row_tiles<NT15, RB, 15>(A);
+        launch_row_q<T, NT15, RB, 15, true, SPLIT>(A, false, st);
+        return OK;
+      }
+      break;
     default: break;
   }
 #undef HM_RW
@@ -649,9 +692,8 @@ int shift_sums_t(const SrePlan &p, const void *psi, const QArgs &qa, uint64_t a0
   }
   for (int l = 0; l < L; ++l) {
     Lane &ln = lane[l];
-    const int thr = 128;
     ProfScope prof("sre_shift_reduce", ln.st);
-    hipLaunchKernelGGL(k_sre_shift_reduce, dim3((unsigned)((ln.prev_nb + thr - 1) / thr)), dim3(thr), 0, ln.st,
+    hipLaunchKernelGGL(k_sre_shift_reduce, dim3(shift_reduce_grid(ln.prev_nb)), dim3(SHIFT_REDUCE_NT), 0, ln.st,
                        ln.partials[(ln.k + 1) & 1], ln.prev_nb, n_cb, nacc, a0 + (uint64_t)ln.prev_s0,
                        rows ? rows + ln.prev_s0 : nullptr, p.nf, qa, shift_sums + ln.prev_s0 * nacc);
   }
@@ -700,8 +742,7 @@ __global__ __launch_bounds__(NT) void k_sre_pair(PairArgs P) {
     rowpass_tiles<T, NT, RB, NL, true, 0, SPLIT>(P.row, t, nr, (typename RS::Elem *)lds_raw, red);
   } else {
     const ColPassArgs &C = P.col;
-    for (int64_t s = t * NT + threadIdx.x; s < C.prev_n_slots; s += nc * NT)
-      reduce_shift(C.prev_partials, s, C.n_cb, C.nacc, C.prev_a0, C.prev_rows, C.nf, C.qa, C.prev_shift_sums);
+    reduce_prev_shifts(C, t * (NT / 64), nc * (NT / 64));
     colpass_tiles<T, NT, RB, NH, CB, QM, SPLIT>(C, t, nc, (typename CS::Elem *)lds_raw, red);
   }
 }
@@ -795,9 +836,8 @@ int pipe_shift_sums_t(const SrePlan &p, const void *psi, const QArgs &qa, uint64
   }
   {
     const int64_t k = nbat - 1;
-    const int thr = 128;
     ProfScope prof("sre_shift_reduce", st);
-    hipLaunchKernelGGL(k_sre_shift_reduce, dim3((unsigned)((bn(k) + thr - 1) / thr)), dim3(thr), 0, st,
+    hipLaunchKernelGGL(k_sre_shift_reduce, dim3(shift_reduce_grid(bn(k))), dim3(SHIFT_REDUCE_NT), 0, st,
                        partials[k & 1], bn(k), n_cb, nacc, a0 + (uint64_t)b0(k), rows ? rows + b0(k) : nullptr, p.nf,
                        qa, shift_sums + b0(k) * nacc);
   }

@@ -211,16 +211,17 @@ static std::vector<PlanOpts> candidates(const hm_context *h, int n, int dbl) {
     if (b == last_b) continue;
     last_b = b;
     for (int split : {1, 2})
-      for (int v = 0; v < 5; ++v) {
+      for (int v = 0; v < 7; ++v) {
+        if (v >= 5 && (dbl || nf < 19)) continue;  // long FP32 rows only where the rows are long
         PlanOpts o{};
         o.force_path = 2;
         o.batch = b;
         o.lds_split = split;
         o.pipeline = v == 4 ? 2 : 1;
-        o.row_bits = v == 1 ? 12 : v == 2 ? 11 : v == 3 ? 13 : 0;
+        o.row_bits = v == 1 ? 12 : v == 2 ? 11 : v == 3 ? 13 : v == 5 ? 14 : v == 6 ? 15 : 0;
         o.streams = 1;
         add(o);
-        if (v < 4) {  // the same on two streams
+        if (v != 4) {  // the same on two streams
           o.streams = 2;
           add(o);
         }

@@ -128,7 +128,7 @@ def test_options_and_forced_paths(L, h):
         assert L.hm_workspace_size(hh, 0, 16, 1, 1, 0, ctypes.byref(b)) == HM_E_UNSUPPORTED  # c128: 2^14
         assert L.hm_set_option(hh, 1, 0) == HM_OK
         assert L.hm_set_option(hh, 3, 3) == HM_E_ARG
-        assert L.hm_set_option(hh, 5, 14) == HM_E_ARG
+        assert L.hm_set_option(hh, 5, 16) == HM_E_ARG
         assert L.hm_set_option(hh, 3, 4) == HM_OK
         assert L.hm_workspace_size(hh, 0, 20, 1, 1, 0, ctypes.byref(b)) == HM_OK
         assert L.hm_set_option(hh, 5, 13) == HM_OK  # row bits 13 leaves 6 for the column pass at n = 20
@@ -389,3 +389,19 @@ def test_qudit_mana_argument_errors(L, h):
     assert L.hm_mana_qudit(h, good, 3, 5, 0, None, ws, 1 << 30, None) == HM_E_ARG
     assert L.hm_mana_qudit(h, good, 3, 5, 0, good, ws, 8, None) == HM_E_WORKSPACE
     assert L.hm_mana_qudit(h, good, 3, 5, 2, good, ws, 1 << 30, None) == HM_E_DTYPE
+
+
+def test_long_row_plans(L, h):
+    """Rows of 2^14 / 2^15 values exist for complex64 only, 2^15 only with split LDS staging."""
+    b = ctypes.c_size_t(0)
+    hh = ctypes.c_void_p()
+    assert L.hm_create(ctypes.byref(hh)) == HM_OK
+    try:
+        assert L.hm_set_option(hh, 1, 2) == HM_OK  # two-pass
+        for rb, dt, split, want in ((15, 0, 0, HM_OK), (14, 0, 0, HM_OK), (15, 0, 1, HM_E_UNSUPPORTED),
+                                    (14, 1, 0, HM_E_UNSUPPORTED), (13, 1, 0, HM_OK)):
+            assert L.hm_set_option(hh, 5, rb) == HM_OK
+            assert L.hm_set_option(hh, 7, split) == HM_OK
+            assert L.hm_workspace_size(hh, 0, 24, dt, 1, 0, ctypes.byref(b)) == want, (rb, dt, split)
+    finally:
+        L.hm_destroy(hh)

@@ -396,6 +396,30 @@ def test_maximum_sizes_sampled_rows(orc, hm, c64, n):
     assert rel_err(got, want, floor=1e-15) < (1e-5 if c64 else 1e-10), (got, want)
 
 
+@pytest.mark.parametrize("n", [22, 24])
+def test_long_rows_at_large_n(orc, hm, n):
+    """From n = 22 the planner gives the complex64 two-pass row pass rows of up to 2^15 values, so
+    that the column tiles stay 2^5 columns wide.  Raw sums over two shift ranges (the a = 0 row and
+    both fold cases) against the oracle, on the default plan and with the row bits forced to 12..15
+    (the split of the previous default and every long-row kernel)."""
+    g = np.random.default_rng(4400 + n)
+    psi = (g.standard_normal(2 ** n) + 1j * g.standard_normal(2 ** n)).astype(np.complex128)
+    psi /= np.linalg.norm(psi)
+    x, w = gpu_state(psi, True)
+    del psi
+    half = 2 ** (n - 1)
+    for a0, a1 in ((0, 24), (half - 5, half + 19)):
+        want = orc.sre_fwht_sums(w, (2.0,), a0, a1)
+        for rb in (0, 12, 13, 14, 15):
+            ctx = hm.Context()
+            ctx.force_path(2)
+            if rb:
+                ctx.set_option(hm.OPT_ROW_BITS, rb)
+            say(f"[sre long rows] n={n} shifts [{a0}, {a1}) row_bits={rb or 'default'}")
+            got = hm.sre_partial(x, (2.0,), a0, a1, ctx=ctx).cpu().numpy()
+            assert rel_err(got, want, floor=1e-12) < 2e-6, (rb, got, want)
+
+
 @pytest.mark.parametrize("k", [1, 4, 16])
 def test_clifford_t_n16_vs_golden(hm, k):
     """Random Clifford circuits with k T gates at seeded positions (n = 16), complex64 values and
