@@ -373,12 +373,14 @@ hm_status hm_mana_qudit(hm_handle h, const void *psi, int n, int d, hm_dtype dty
 
 /* Mana of a mixed state (Sec. "Mana of mixed states via a fast tensor-product transform", Eq.
  * MN_factor_mana and its Algorithm): all 9^n values w_u = Tr(rho A_u) as the tensor power of a 9 x 9
- * single-qutrit matrix applied to the reordered density matrix, one HBM-streaming pass per qutrit.
+ * single-qutrit matrix applied to the reordered density matrix, several qutrits per HBM-streaming
+ * pass (qutrits 0..2 in the pass that reorders rho, then two per pass, the last pass summing instead
+ * of writing).
  * rho: device, 3^n x 3^n row-major (rho[r 3^n + c] = <r|rho|c>, qutrit k = base-3 digit k of r and c),
  * Hermitian (not checked; the imaginary parts of w are dropped).  out: device, 3 doubles
  * = {mana = log2(sum_u |w_u| / 3^n), sum_u W(u) = Tr rho, 3^n sum_u W(u)^2 = Tr rho^2} with
  * W = w / 3^n.  1 <= n <= 10.  Workspace: hm_workspace_size(HM_OP_MANA_MIXED): the reordered
- * 9^n-value copy of rho (HM_C128 at n = 10: 56 GB) plus 2 x 3^n digit tables. */
+ * 9^n-value copy of rho (HM_C128 at n = 10: 56 GB) plus 48 KB of partial sums. */
 hm_status hm_mana_mixed(hm_handle h, const void *rho, int n, hm_dtype dtype, double *out, void *ws, size_t ws_bytes,
                         hipStream_t stream);
 

@@ -159,7 +159,7 @@ size_t sre_workspace(const SrePlan &p, int nq, int64_t n_internal_slots);
 int sre_run(const SrePlan &p, const void *psi, const QArgs &qa, uint64_t a0, const uint64_t *rows, int64_t n_slots,
             double *ext_shift_sums, double *sums, double *out, void *ws, hipStream_t stream);
 int sre_reduce_shifts(const double *shift_sums, int64_t n_slots, const QArgs &qa, int N, double *sums, double *out,
-                      hipStream_t stream);
+                      hipStream_t stream, double *scratch = nullptr, size_t scratch_bytes = 0);
 // Many states of one size n on the workgroup-resident path: per-shift sums of all shifts of the
 // n_states states (pointers psis) in one launch, then one fixed-order total per state into
 // outs[s][0..nq] = {M_q..., lost_norm}.

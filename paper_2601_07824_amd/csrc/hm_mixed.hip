@@ -4,11 +4,17 @@
 //
 // All 9^N values w_u = Tr(rho A_u) are one tensor power of a 9 x 9 single-qutrit matrix applied to the
 // vectorised density matrix.  On the GPU the density matrix (row-major, rho[r 3^N + c] = <r|rho|c>,
-// qutrit k = base-3 digit k of r and c) is first reordered so that qutrit k's pair (r_k, c_k) is the
-// base-9 digit k of the position (p = sum_k (3 r_k + c_k) 9^k); then one HBM-streaming pass per qutrit
-// applies the single-qutrit matrix to every fibre of 9 values along that digit, in place.  The pass
-// over the last digit (the fibres are 9 consecutive values) does not write back: it reduces
-// sum_u |w_u|, sum_u w_u and sum_u w_u^2 in FP64 (fixed order) instead.
+// qutrit k = base-3 digit k of r and c) is reordered so that qutrit k's pair (r_k, c_k) is the base-9
+// digit k of the position (p = sum_k (3 r_k + c_k) 9^k), and the single-qutrit matrix is applied along
+// every digit.  Several digits share one HBM-streaming pass through LDS:
+//   * pass A reads a 27 x 27 block of rho (qutrits 0..2 of its rows and columns vary, 27 contiguous
+//     columns per row), reorders it in LDS, applies the matrix along digits 0, 1, 2 and writes the
+//     729 values contiguously (the reordering costs no pass of its own);
+//   * each pass B takes digits k, k + 1 with digit 0 along for contiguous 144-B segments (9 x 81
+//     values per tile), in place;
+//   * the last pass does not write back: it reduces sum_u |w_u|, sum_u w_u and sum_u w_u^2 in FP64
+//     (fixed order) instead.
+// N = 8 thus streams the 9^N values 4 times (read + write 3 times, read once) instead of N + 1.
 //
 // The single-qutrit matrix, from A_ab|x> = omega^{2b(a-x)} |2a - x> (the phase-space point operators of
 // Eq. phase-space up to a relabelling of the points): with x_mu = rho_{r,c} at mu = 3 r + c,
@@ -23,30 +29,6 @@
 #include "hm_tile.h"
 
 namespace hm {
-
-// 9^k positions of the reordered vector: contributions of a row index r and a column index c.
-__global__ void k_mixed_digits(int n, uint64_t D, uint64_t *pr, uint64_t *pc) {
-  const uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= D) return;
-  uint64_t v = x, r = 0, c = 0, w = 1;
-  for (int k = 0; k < n; ++k, w *= 9, v /= 3) {
-    r += 3 * (v % 3) * w;
-    c += (v % 3) * w;
-  }
-  pr[x] = r;
-  pc[x] = c;
-}
-
-// v[pr[r] + pc[c]] = rho[r D + c]: one block row of 256 columns per thread block (coalesced reads).
-template <typename T>
-__global__ __launch_bounds__(256) void k_mixed_vec(const vec2<T> *rho, uint64_t D, const uint64_t *pr,
-                                                   const uint64_t *pc, vec2<T> *v) {
-  const uint64_t r = blockIdx.y + ((uint64_t)blockIdx.z << 16);
-  if (r >= D) return;
-  const uint64_t base = pr[r];
-  for (uint64_t c = (uint64_t)blockIdx.x * 256 + threadIdx.x; c < D; c += (uint64_t)gridDim.x * 256)
-    v[base + pc[c]] = rho[r * D + c];
-}
 
 // The single-qutrit transform of one fibre x[0..8] -> y[0..8].
 template <typename T>
@@ -75,51 +57,136 @@ __device__ __forceinline__ void mixed_fibre(const vec2<T> (&x)[9], vec2<T> (&y)[
     }
 }
 
-// One pass along base-9 digit k (stride 9^k), in place.  Thread f owns fibre f.
+static constexpr int MIXED_NT = 256;
+static constexpr int MIXED_RED_BLOCKS = 2048;
+
+// Fibres of 9 values at stride `st` inside an LDS tile: fibre f (f < nfib) starts at
+// (f / st) * 9 st + f % st; thread t takes fibres t, t + MIXED_NT, ...
 template <typename T>
-__global__ __launch_bounds__(256) void k_mixed_leg(vec2<T> *v, uint64_t n_fibres, uint64_t stride) {
-  for (uint64_t f = (uint64_t)blockIdx.x * 256 + threadIdx.x; f < n_fibres; f += (uint64_t)gridDim.x * 256) {
-    const uint64_t base = (f / stride) * stride * 9 + f % stride;
+__device__ __forceinline__ void lds_digit(vec2<T> *t, int nfib, int st) {
+  for (int f = threadIdx.x; f < nfib; f += MIXED_NT) {
+    const int base = (f / st) * st * 9 + f % st;
     vec2<T> x[9], y[9];
 #pragma unroll
-    for (int a = 0; a < 9; ++a) x[a] = v[base + a * stride];
+    for (int a = 0; a < 9; ++a) x[a] = t[base + a * st];
     mixed_fibre<T>(x, y);
 #pragma unroll
-    for (int a = 0; a < 9; ++a) v[base + a * stride] = y[a];
+    for (int a = 0; a < 9; ++a) t[base + a * st] = y[a];
   }
 }
 
-// The pass along digit 0 (fibres of 9 consecutive values) with the reduction instead of a write:
-// per-block FP64 partials {sum |w|, sum w, sum w^2} of the real parts (w is real for a Hermitian rho).
-static constexpr int MIXED_RED_BLOCKS = 2048;
+// FP64 sums {sum |w|, sum w, sum w^2} of the real parts of the tile's n values into acc.
 template <typename T>
-__global__ __launch_bounds__(256) void k_mixed_last(const vec2<T> *v, uint64_t n_fibres, double *part) {
-  __shared__ double red[3][256];
-  double m = 0.0, s = 0.0, q = 0.0;
-  for (uint64_t f = (uint64_t)blockIdx.x * 256 + threadIdx.x; f < n_fibres; f += (uint64_t)gridDim.x * 256) {
-    vec2<T> x[9], y[9];
-#pragma unroll
-    for (int a = 0; a < 9; ++a) x[a] = v[f * 9 + a];
-    mixed_fibre<T>(x, y);
-#pragma unroll
-    for (int a = 0; a < 9; ++a) {
-      const double w = (double)y[a].x;
-      m += fabs(w);
-      s += w;
-      q = fma(w, w, q);
-    }
+__device__ __forceinline__ void lds_sums(const vec2<T> *t, int n, double (&acc)[3]) {
+  for (int e = threadIdx.x; e < n; e += MIXED_NT) {
+    const double w = (double)t[e].x;  // real for a Hermitian rho
+    acc[0] += fabs(w);
+    acc[1] += w;
+    acc[2] = fma(w, w, acc[2]);
   }
-  red[0][threadIdx.x] = m;
-  red[1][threadIdx.x] = s;
-  red[2][threadIdx.x] = q;
+}
+
+// Fixed-order workgroup sums of acc into part[blockIdx.x].
+__device__ __forceinline__ void block_sums_out(double (&acc)[3], double *part) {
+  __shared__ double red[3][MIXED_NT];
+  for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = acc[k];
   __syncthreads();
-  for (unsigned w = 128; w > 0; w >>= 1) {
+  for (unsigned w = MIXED_NT / 2; w > 0; w >>= 1) {
     if (threadIdx.x < w)
       for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
     __syncthreads();
   }
   if (threadIdx.x == 0)
     for (int k = 0; k < 3; ++k) part[blockIdx.x * 3 + k] = red[k][0];
+}
+
+// Pass A: tile q (q < 9^(N - M)) is the 3^M x 3^M block of rho whose rows and columns share the
+// base-3 digits M.. of q's pairs (mu_k = 3 r_k + c_k = base-9 digit k - M of q); in LDS it is
+// reordered to p_lo = sum_{j < M} mu_j 9^j and transformed along digits 0..M-1, then written to
+// v[q 9^M + p_lo] (REDUCE: summed instead).  M = min(N, 3).
+template <typename T, int M, bool REDUCE>
+__global__ __launch_bounds__(MIXED_NT) void k_mixed_first(const vec2<T> *__restrict__ rho, uint64_t D, uint64_t n_tiles,
+                                                           vec2<T> *__restrict__ v, double *part) {
+  constexpr int B = M == 1 ? 3 : M == 2 ? 9 : 27;  // 3^M
+  constexpr int TILE = B * B;                       // 9^M
+  __shared__ vec2<T> t[TILE];
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (uint64_t q = blockIdx.x; q < n_tiles; q += gridDim.x) {
+    // high row / column parts of the block
+    uint64_t R = 0, C = 0, w3 = B, qq = q;
+    while (qq) {
+      const uint32_t mu = (uint32_t)(qq % 9);
+      qq /= 9;
+      R += (mu / 3) * w3;
+      C += (mu % 3) * w3;
+      w3 *= 3;
+    }
+    __syncthreads();  // the previous tile's LDS reads are done
+    for (int e = threadIdx.x; e < TILE; e += MIXED_NT) {
+      const int rl = e / B, cl = e % B;  // row-major within the block: B contiguous columns per row
+      int p = 0, w9 = 1, r = rl, c = cl;
+#pragma unroll
+      for (int j = 0; j < M; ++j, w9 *= 9, r /= 3, c /= 3) p += (3 * (r % 3) + (c % 3)) * w9;
+      t[p] = rho[(R + rl) * D + C + cl];
+    }
+    __syncthreads();
+    lds_digit<T>(t, TILE / 9, 1);
+    if constexpr (M >= 2) {
+      __syncthreads();
+      lds_digit<T>(t, TILE / 9, 9);
+    }
+    if constexpr (M >= 3) {
+      __syncthreads();
+      lds_digit<T>(t, TILE / 9, 81);
+    }
+    __syncthreads();
+    if constexpr (REDUCE) {
+      lds_sums<T>(t, TILE, acc);
+    } else {
+      vec2<T> *o = v + q * TILE;
+      for (int e = threadIdx.x; e < TILE; e += MIXED_NT) o[e] = t[e];
+    }
+  }
+  if constexpr (REDUCE) block_sums_out(acc, part);
+}
+
+// Pass B: digits k and k + 1 (ND = 2) or k alone (ND = 1), with digit 0 carried along: tile q holds
+// the 9 x 9^ND values base + j0 + sum_{i < ND} mu_i 9^(k + i), base = (q mod 9^(k-1)) 9 +
+// (q div 9^(k-1)) 9^(k+ND); LDS layout [mu_{k+1}][mu_k][j0].  In place, or summed (REDUCE).
+template <typename T, int ND, bool REDUCE>
+__global__ __launch_bounds__(MIXED_NT) void k_mixed_pair(vec2<T> *__restrict__ v, uint64_t n_tiles, uint64_t lo_span,
+                                                          uint64_t stride_k, double *part) {
+  constexpr int TILE = ND == 2 ? 729 : 81;
+  __shared__ vec2<T> t[TILE];
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (uint64_t q = blockIdx.x; q < n_tiles; q += gridDim.x) {
+    const uint64_t base = (q % lo_span) * 9 + (q / lo_span) * stride_k * (ND == 2 ? 81 : 9);
+    __syncthreads();
+    for (int e = threadIdx.x; e < TILE; e += MIXED_NT) {
+      const int j0 = e % 9, m = e / 9;  // m = mu_k + 9 mu_{k+1}
+      const uint64_t off = ND == 2 ? (uint64_t)(m % 9) * stride_k + (uint64_t)(m / 9) * stride_k * 9
+                                   : (uint64_t)m * stride_k;
+      t[e] = v[base + j0 + off];
+    }
+    __syncthreads();
+    lds_digit<T>(t, TILE / 9, 9);
+    if constexpr (ND == 2) {
+      __syncthreads();
+      lds_digit<T>(t, TILE / 9, 81);
+    }
+    __syncthreads();
+    if constexpr (REDUCE) {
+      lds_sums<T>(t, TILE, acc);
+    } else {
+      for (int e = threadIdx.x; e < TILE; e += MIXED_NT) {
+        const int j0 = e % 9, m = e / 9;
+        const uint64_t off = ND == 2 ? (uint64_t)(m % 9) * stride_k + (uint64_t)(m / 9) * stride_k * 9
+                                     : (uint64_t)m * stride_k;
+        v[base + j0 + off] = t[e];
+      }
+    }
+  }
+  if constexpr (REDUCE) block_sums_out(acc, part);
 }
 
 __global__ __launch_bounds__(256) void k_mixed_total(const double *part, int nblk, int N, double *out) {
@@ -169,41 +236,60 @@ static uint64_t pow_u(uint64_t b, int e) {
   return r;
 }
 
-// [digit tables pr, pc (2 x 3^N u64)][partials][reordered vector 9^N values]
+// [partials][reordered vector 9^N values]
 int mixed_workspace(int N, int dbl, size_t *bytes) {
   if (N < 1 || N > 10) return fail(E_SIZE, "mixed mana: n = %d outside [1, 10]", N);
   const uint64_t D = pow_u(3, N);
-  *bytes = 2 * align256(D * 8) + align256(MIXED_RED_BLOCKS * 3 * sizeof(double)) + align256(D * D * (dbl ? 16 : 8));
+  *bytes = align256(MIXED_RED_BLOCKS * 3 * sizeof(double)) + align256(D * D * (dbl ? 16 : 8));
   return OK;
+}
+
+static unsigned grid_of(uint64_t tiles, uint64_t cap) { return (unsigned)(tiles < cap ? tiles : cap); }
+
+template <typename T, int M>
+static void launch_first(bool reduce, const void *rho, uint64_t D, uint64_t tiles, vec2<T> *v, double *part,
+                         unsigned *red_grid, hipStream_t st) {
+  ProfScope prof(reduce ? "mixed_last" : "mixed_first", st);
+  if (reduce) {
+    *red_grid = grid_of(tiles, MIXED_RED_BLOCKS);
+    hipLaunchKernelGGL((k_mixed_first<T, M, true>), dim3(*red_grid), dim3(MIXED_NT), 0, st, (const vec2<T> *)rho, D,
+                       tiles, v, part);
+  } else {
+    hipLaunchKernelGGL((k_mixed_first<T, M, false>), dim3(grid_of(tiles, 1u << 20)), dim3(MIXED_NT), 0, st,
+                       (const vec2<T> *)rho, D, tiles, v, part);
+  }
 }
 
 template <typename T>
 static int mixed_t(int N, const void *rho, double *out, void *ws, hipStream_t st) {
-  const uint64_t D = pow_u(3, N);
+  const uint64_t D = pow_u(3, N), V = D * D;
   char *w = (char *)ws;
-  uint64_t *pr = (uint64_t *)w;
-  uint64_t *pc = (uint64_t *)(w + align256(D * 8));
-  double *part = (double *)(w + 2 * align256(D * 8));
-  vec2<T> *v = (vec2<T> *)(w + 2 * align256(D * 8) + align256(MIXED_RED_BLOCKS * 3 * sizeof(double)));
-  hipLaunchKernelGGL(k_mixed_digits, dim3((unsigned)((D + 255) / 256)), dim3(256), 0, st, N, D, pr, pc);
-  {
-    ProfScope prof("mixed_vec", st);
-    const unsigned gx = (unsigned)((D + 255) / 256 < 64 ? (D + 255) / 256 : 64);
-    hipLaunchKernelGGL(k_mixed_vec<T>, dim3(gx, (unsigned)(D < 65536 ? D : 65536), (unsigned)((D + 65535) >> 16)),
-                       dim3(256), 0, st, (const vec2<T> *)rho, D, (const uint64_t *)pr, (const uint64_t *)pc, v);
+  double *part = (double *)w;
+  vec2<T> *v = (vec2<T> *)(w + align256(MIXED_RED_BLOCKS * 3 * sizeof(double)));
+  const int M = N < 3 ? N : 3;
+  const uint64_t tiles_a = V / pow_u(9, M);
+  unsigned red_grid = 0;
+  if (M == 1) launch_first<T, 1>(N == M, rho, D, tiles_a, v, part, &red_grid, st);
+  else if (M == 2) launch_first<T, 2>(N == M, rho, D, tiles_a, v, part, &red_grid, st);
+  else launch_first<T, 3>(N == M, rho, D, tiles_a, v, part, &red_grid, st);
+  for (int k = M; k < N;) {
+    const int nd = N - k >= 2 ? 2 : 1;
+    const bool last = k + nd == N;
+    const uint64_t tiles = V / pow_u(9, nd + 1), lo_span = pow_u(9, k - 1), stride_k = pow_u(9, k);
+    ProfScope prof(last ? "mixed_last" : "mixed_pair", st);
+    if (last) {
+      red_grid = grid_of(tiles, MIXED_RED_BLOCKS);
+      if (nd == 2)
+        hipLaunchKernelGGL((k_mixed_pair<T, 2, true>), dim3(red_grid), dim3(MIXED_NT), 0, st, v, tiles, lo_span, stride_k, part);
+      else
+        hipLaunchKernelGGL((k_mixed_pair<T, 1, true>), dim3(red_grid), dim3(MIXED_NT), 0, st, v, tiles, lo_span, stride_k, part);
+    } else {
+      hipLaunchKernelGGL((k_mixed_pair<T, 2, false>), dim3(grid_of(tiles, 1u << 20)), dim3(MIXED_NT), 0, st, v, tiles,
+                         lo_span, stride_k, part);
+    }
+    k += nd;
   }
-  const uint64_t nf = D * D / 9;
-  const unsigned grid = (unsigned)((nf + 255) / 256 < 16384 ? (nf + 255) / 256 : 16384);
-  uint64_t stride = D * D / 9;  // 9^(N-1): the highest digit first
-  for (int k = N - 1; k >= 1; --k, stride /= 9) {
-    ProfScope prof("mixed_leg", st);
-    hipLaunchKernelGGL(k_mixed_leg<T>, dim3(grid), dim3(256), 0, st, v, nf, stride);
-  }
-  {
-    ProfScope prof("mixed_last", st);
-    hipLaunchKernelGGL(k_mixed_last<T>, dim3(MIXED_RED_BLOCKS), dim3(256), 0, st, (const vec2<T> *)v, nf, part);
-  }
-  hipLaunchKernelGGL(k_mixed_total, dim3(1), dim3(256), 0, st, (const double *)part, MIXED_RED_BLOCKS, N, out);
+  hipLaunchKernelGGL(k_mixed_total, dim3(1), dim3(256), 0, st, (const double *)part, (int)red_grid, N, out);
   return hipPeekAtLastError() == hipSuccess ? OK : fail(E_HIP, "mixed mana launch: %s", hipGetErrorString(hipGetLastError()));
 }
 

@@ -125,19 +125,17 @@ __global__ __launch_bounds__(256) void k_sre_sampled_stats(const double *row_sum
   }
 }
 
-// Fixed-order sum over all per-shift sums; optionally finalise (Eq. sre).  Thread t adds the rows
+// Fixed-order sum of rows [0, n) of nacc doubles by one workgroup: thread t adds the rows
 // t, t + TOT_NT, ... (all nacc slots of a row at once), then a tree over the threads per slot.
+// tot[k] (shared) receives the sums.
 static constexpr int TOT_NT = 1024;
-__global__ __launch_bounds__(TOT_NT) void k_sre_total(const double *shift_sums, int64_t n_slots, int nacc, QArgs qa,
-                                                      int N, double *sums, double *out) {
-  __shared__ double red[TOT_NT];
-  __shared__ double tot[HM_MAX_Q + 1];
+__device__ __forceinline__ void block_rows_sum(const double *rows_, int64_t n, int nacc, double *red, double *tot) {
   const uint32_t t = threadIdx.x;
   double s[HM_MAX_Q + 1];
 #pragma unroll
   for (int k = 0; k <= HM_MAX_Q; ++k) s[k] = 0.0;
-  for (int64_t i = t; i < n_slots; i += TOT_NT) {
-    const double *row = shift_sums + i * nacc;
+  for (int64_t i = t; i < n; i += TOT_NT) {
+    const double *row = rows_ + i * nacc;
 #pragma unroll
     for (int k = 0; k <= HM_MAX_Q; ++k)
       if (k < nacc) s[k] += row[k];
@@ -155,7 +153,28 @@ __global__ __launch_bounds__(TOT_NT) void k_sre_total(const double *shift_sums, 
       __syncthreads();
     }
   }
-  if (t == 0) {
+}
+
+// First level for long shift lists: workgroup g sums the contiguous chunk of rows
+// [g chunk, (g + 1) chunk) into part[g] (fixed order within and across workgroups).
+__global__ __launch_bounds__(TOT_NT) void k_sre_total_part(const double *shift_sums, int64_t n_slots, int nacc,
+                                                           int64_t chunk, double *part) {
+  __shared__ double red[TOT_NT];
+  __shared__ double tot[HM_MAX_Q + 1];
+  const int64_t r0 = (int64_t)blockIdx.x * chunk;
+  const int64_t n = r0 >= n_slots ? 0 : (n_slots - r0 < chunk ? n_slots - r0 : chunk);
+  block_rows_sum(shift_sums + r0 * nacc, n, nacc, red, tot);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < nacc; ++k) part[blockIdx.x * nacc + k] = tot[k];
+}
+
+// Fixed-order sum over all per-shift sums (or first-level partials); optionally finalise (Eq. sre).
+__global__ __launch_bounds__(TOT_NT) void k_sre_total(const double *shift_sums, int64_t n_slots, int nacc, QArgs qa,
+                                                      int N, double *sums, double *out) {
+  __shared__ double red[TOT_NT];
+  __shared__ double tot[HM_MAX_Q + 1];
+  block_rows_sum(shift_sums, n_slots, nacc, red, tot);
+  if (threadIdx.x == 0) {
     if (sums)
       for (int k = 0; k < nacc; ++k) sums[k] = tot[k];
     if (out) {
@@ -294,14 +313,32 @@ int sre_run(const SrePlan &p, const void *psi, const QArgs &qa, uint64_t a0, con
   int e = p.dbl ? sre_shift_sums_f64(p, psi, qa, a0, rows, n_slots, ss, w, st)
                 : sre_shift_sums_f32(p, psi, qa, a0, rows, n_slots, ss, w, st);
   if (e) return e;
-  if (sums || out) return sre_reduce_shifts(ss, n_slots, qa, p.N, sums, out, st);
+  if (sums || out) {
+    // the two-pass path's exchange region is free again once the shift sums are written (stream
+    // order) and holds the first-level partials of a long shift list
+    const size_t spare = p.path == 2 ? sre_exch_bytes(p) : 0;
+    return sre_reduce_shifts(ss, n_slots, qa, p.N, sums, out, st, (double *)w, spare);
+  }
   return OK;
 }
 
+// Above 2^18 shifts the sum runs in two levels (TOT_PARTS workgroups over contiguous chunks, then
+// one over their partials) where scratch for the partials is given; one workgroup otherwise.
+static constexpr int64_t TOT_TWO_LEVEL = (int64_t)1 << 18;
+static constexpr int TOT_PARTS = 512;
+
 int sre_reduce_shifts(const double *shift_sums, int64_t n_slots, const QArgs &qa, int N, double *sums, double *out,
-                      hipStream_t st) {
+                      hipStream_t st, double *scratch, size_t scratch_bytes) {
   ProfScope prof("sre_total", st);
-  hipLaunchKernelGGL(k_sre_total, dim3(1), dim3(TOT_NT), 0, st, shift_sums, n_slots, nacc_of(qa), qa, N, sums, out);
+  const int nacc = nacc_of(qa);
+  if (n_slots > TOT_TWO_LEVEL && scratch && scratch_bytes >= (size_t)TOT_PARTS * nacc * sizeof(double)) {
+    const int64_t chunk = (n_slots + TOT_PARTS - 1) / TOT_PARTS;
+    hipLaunchKernelGGL(k_sre_total_part, dim3(TOT_PARTS), dim3(TOT_NT), 0, st, shift_sums, n_slots, nacc, chunk, scratch);
+    hipLaunchKernelGGL(k_sre_total, dim3(1), dim3(TOT_NT), 0, st, (const double *)scratch, (int64_t)TOT_PARTS, nacc, qa,
+                       N, sums, out);
+  } else {
+    hipLaunchKernelGGL(k_sre_total, dim3(1), dim3(TOT_NT), 0, st, shift_sums, n_slots, nacc, qa, N, sums, out);
+  }
   return hipPeekAtLastError() == hipSuccess ? OK : fail(E_HIP, "SRE reduce launch: %s", hipGetErrorString(hipGetLastError()));
 }
 
