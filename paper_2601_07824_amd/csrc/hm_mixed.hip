@@ -11,7 +11,7 @@
 //     columns per row), reorders it in LDS, applies the matrix along digits 0, 1, 2 and writes the
 //     729 values contiguously (the reordering costs no pass of its own);
 //   * each pass B takes digits k, k + 1 with digit 0 along for contiguous 144-B segments (9 x 81
-//     values per tile), in place;
+//     values per tile), in place (a last single digit takes digits 0 and 1 along);
 //   * the last pass does not write back: it reduces sum_u |w_u|, sum_u w_u and sum_u w_u^2 in FP64
 //     (fixed order) instead.
 // N = 8 thus streams the 9^N values 4 times (read + write 3 times, read once) instead of N + 1.
@@ -111,7 +111,9 @@ __global__ __launch_bounds__(MIXED_NT) void k_mixed_first(const vec2<T> *__restr
   constexpr int TILE = B * B;                       // 9^M
   __shared__ vec2<T> t[TILE];
   double acc[3] = {0.0, 0.0, 0.0};
-  for (uint64_t q = blockIdx.x; q < n_tiles; q += gridDim.x) {
+  for (uint64_t b = blockIdx.x; b < n_tiles; b += gridDim.x) {
+    // neighbouring blocks share cache lines at their edges: keep them on one XCD's L2
+    const uint64_t q = (uint64_t)xcd_tile((int64_t)b, (int64_t)n_tiles);
     // high row / column parts of the block
     uint64_t R = 0, C = 0, w3 = B, qq = q;
     while (qq) {
@@ -150,40 +152,40 @@ __global__ __launch_bounds__(MIXED_NT) void k_mixed_first(const vec2<T> *__restr
   if constexpr (REDUCE) block_sums_out(acc, part);
 }
 
-// Pass B: digits k and k + 1 (ND = 2) or k alone (ND = 1), with digit 0 carried along: tile q holds
-// the 9 x 9^ND values base + j0 + sum_{i < ND} mu_i 9^(k + i), base = (q mod 9^(k-1)) 9 +
-// (q div 9^(k-1)) 9^(k+ND); LDS layout [mu_{k+1}][mu_k][j0].  In place, or summed (REDUCE).
-template <typename T, int ND, bool REDUCE>
+// Pass B: digits k and k + 1 (ND = 2) or k alone (ND = 1), with the P lowest digits carried along
+// so that a tile reads contiguous segments of 9^P values (144 B for P = 1, 1296 B for P = 2) and
+// holds 9^(ND + P) = 729 values: tile q covers base + j + sum_{i < ND} mu_i 9^(k + i), j < 9^P,
+// base = (q mod 9^(k-P)) 9^P + (q div 9^(k-P)) 9^(k+ND); LDS layout [mu_{k+1}][mu_k][j].  In place,
+// or summed (REDUCE).
+template <typename T, int ND, int P, bool REDUCE>
 __global__ __launch_bounds__(MIXED_NT) void k_mixed_pair(vec2<T> *__restrict__ v, uint64_t n_tiles, uint64_t lo_span,
                                                           uint64_t stride_k, double *part) {
-  constexpr int TILE = ND == 2 ? 729 : 81;
+  constexpr int PS = P == 1 ? 9 : 81;           // 9^P
+  constexpr int TILE = PS * (ND == 2 ? 81 : 9);  // 9^(ND + P)
   __shared__ vec2<T> t[TILE];
   double acc[3] = {0.0, 0.0, 0.0};
-  for (uint64_t q = blockIdx.x; q < n_tiles; q += gridDim.x) {
-    const uint64_t base = (q % lo_span) * 9 + (q / lo_span) * stride_k * (ND == 2 ? 81 : 9);
+  auto off = [&](int e) -> uint64_t {
+    const int j = e % PS, m = e / PS;  // m = mu_k + 9 mu_{k+1}
+    return (uint64_t)j + (ND == 2 ? (uint64_t)(m % 9) * stride_k + (uint64_t)(m / 9) * stride_k * 9
+                                  : (uint64_t)m * stride_k);
+  };
+  for (uint64_t b = blockIdx.x; b < n_tiles; b += gridDim.x) {
+    // consecutive tiles share the cache lines their segments straddle: keep them on one XCD's L2
+    const uint64_t q = (uint64_t)xcd_tile((int64_t)b, (int64_t)n_tiles);
+    const uint64_t base = (q % lo_span) * PS + (q / lo_span) * stride_k * (ND == 2 ? 81 : 9);
     __syncthreads();
-    for (int e = threadIdx.x; e < TILE; e += MIXED_NT) {
-      const int j0 = e % 9, m = e / 9;  // m = mu_k + 9 mu_{k+1}
-      const uint64_t off = ND == 2 ? (uint64_t)(m % 9) * stride_k + (uint64_t)(m / 9) * stride_k * 9
-                                   : (uint64_t)m * stride_k;
-      t[e] = v[base + j0 + off];
-    }
+    for (int e = threadIdx.x; e < TILE; e += MIXED_NT) t[e] = v[base + off(e)];
     __syncthreads();
-    lds_digit<T>(t, TILE / 9, 9);
+    lds_digit<T>(t, TILE / 9, PS);
     if constexpr (ND == 2) {
       __syncthreads();
-      lds_digit<T>(t, TILE / 9, 81);
+      lds_digit<T>(t, TILE / 9, PS * 9);
     }
     __syncthreads();
     if constexpr (REDUCE) {
       lds_sums<T>(t, TILE, acc);
     } else {
-      for (int e = threadIdx.x; e < TILE; e += MIXED_NT) {
-        const int j0 = e % 9, m = e / 9;
-        const uint64_t off = ND == 2 ? (uint64_t)(m % 9) * stride_k + (uint64_t)(m / 9) * stride_k * 9
-                                     : (uint64_t)m * stride_k;
-        v[base + j0 + off] = t[e];
-      }
+      for (int e = threadIdx.x; e < TILE; e += MIXED_NT) v[base + off(e)] = t[e];
     }
   }
   if constexpr (REDUCE) block_sums_out(acc, part);
@@ -244,6 +246,8 @@ int mixed_workspace(int N, int dbl, size_t *bytes) {
   return OK;
 }
 
+// One workgroup per tile, or a grid-stride loop over `cap` workgroups (a multiple of 8, so that the
+// tiles a workgroup takes stay on its XCD's share).
 static unsigned grid_of(uint64_t tiles, uint64_t cap) { return (unsigned)(tiles < cap ? tiles : cap); }
 
 template <typename T, int M>
@@ -273,18 +277,21 @@ static int mixed_t(int N, const void *rho, double *out, void *ws, hipStream_t st
   else if (M == 2) launch_first<T, 2>(N == M, rho, D, tiles_a, v, part, &red_grid, st);
   else launch_first<T, 3>(N == M, rho, D, tiles_a, v, part, &red_grid, st);
   for (int k = M; k < N;) {
-    const int nd = N - k >= 2 ? 2 : 1;
+    // two digits with digit 0 carried along, or (the last digit alone) one with digits 0 and 1
+    const int nd = N - k >= 2 ? 2 : 1, P = nd == 2 ? 1 : 2;
     const bool last = k + nd == N;
-    const uint64_t tiles = V / pow_u(9, nd + 1), lo_span = pow_u(9, k - 1), stride_k = pow_u(9, k);
+    const uint64_t tiles = V / pow_u(9, nd + P), lo_span = pow_u(9, k - P), stride_k = pow_u(9, k);
     ProfScope prof(last ? "mixed_last" : "mixed_pair", st);
     if (last) {
       red_grid = grid_of(tiles, MIXED_RED_BLOCKS);
       if (nd == 2)
-        hipLaunchKernelGGL((k_mixed_pair<T, 2, true>), dim3(red_grid), dim3(MIXED_NT), 0, st, v, tiles, lo_span, stride_k, part);
+        hipLaunchKernelGGL((k_mixed_pair<T, 2, 1, true>), dim3(red_grid), dim3(MIXED_NT), 0, st, v, tiles, lo_span,
+                           stride_k, part);
       else
-        hipLaunchKernelGGL((k_mixed_pair<T, 1, true>), dim3(red_grid), dim3(MIXED_NT), 0, st, v, tiles, lo_span, stride_k, part);
+        hipLaunchKernelGGL((k_mixed_pair<T, 1, 2, true>), dim3(red_grid), dim3(MIXED_NT), 0, st, v, tiles, lo_span,
+                           stride_k, part);
     } else {
-      hipLaunchKernelGGL((k_mixed_pair<T, 2, false>), dim3(grid_of(tiles, 1u << 20)), dim3(MIXED_NT), 0, st, v, tiles,
+      hipLaunchKernelGGL((k_mixed_pair<T, 2, 1, false>), dim3(grid_of(tiles, 1u << 20)), dim3(MIXED_NT), 0, st, v, tiles,
                          lo_span, stride_k, part);
     }
     k += nd;
