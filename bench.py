@@ -192,6 +192,17 @@ def exchange_roofline(prof, fam_bytes: dict, work_values: float):
             "frac": round(bpl / t_launch / 1e9 / HBM_PEAK_GBS, 4)}
 
 
+def mixed_pass_bytes(na: int, value_bytes: int = 16) -> float:
+    """Bytes the mixed-state mana streams through HBM: the first pass reads rho and writes the
+    reordered copy (qutrits 0..2), each further pass but the last reads and writes it (two qutrits),
+    the last reads it; 9^na values each time."""
+    m = min(na, 3)
+    rest = na - m
+    passes = (rest + 1) // 2
+    units = (1 if passes == 0 else 2) + 2 * max(passes - 1, 0) + (1 if passes else 0)
+    return units * 9.0 ** na * value_bytes
+
+
 def secondary(hm, S, torch, dev, psi, N):
     """The other rows of the metric, each timed once after a warm-up call (wall clock around the
     call, state resident; plans autotuned where noted): complex128 forward at the headline N
@@ -324,8 +335,8 @@ def secondary(hm, S, torch, dev, psi, N):
             sec["mana_mixed_na%d_c128" % na] = {"ms": dt * 1e3, "mana": float(o[0].item()), "trace": float(o[1].item()),
                                                 "purity": float(o[2].item()), "value": 9.0 ** na / dt,
                                                 "unit": "phase-space points/s",
-                                                "hbm_bytes": (2 * na + 1) * 9.0 ** na * 16,
-                                                "hbm_frac": (2 * na + 1) * 9.0 ** na * 16 / dt / 1e9 / HBM_PEAK_GBS}
+                                                "hbm_bytes": mixed_pass_bytes(na),
+                                                "hbm_frac": mixed_pass_bytes(na) / dt / 1e9 / HBM_PEAK_GBS}
             del rho
         # pure-state mana of qudits of odd prime dimension at the largest sizes of the LDS-resident
         # kernel (Gaussian states): d^(2n) phase-space points per evaluation
