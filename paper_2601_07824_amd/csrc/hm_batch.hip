@@ -75,7 +75,7 @@ __device__ __noinline__ void batch_tile(const void *psi, int nf, double *shift_s
     const StateTileArgs A(psi, nf, shift_sums, nacc, t + 1, qa);
     T *lds = (T *)batch_lds;
     double *red = batch_lds + BatchShape<T, NT, RB>::TILE_BYTES / 8;
-    rowpass_tiles<T, NT, RB, NL, false, QM, true, StateTileArgs>(A, t, 1, lds, red, tau);
+    rowpass_tiles<T, NT, RB, NL, false, QM, true, StateTileArgs, true>(A, t, 1, lds, red, tau);
   }
 }
 

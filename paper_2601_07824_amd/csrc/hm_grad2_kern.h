@@ -24,7 +24,7 @@ __global__ __launch_bounds__(NT) void k_sre_colpass_adj(ColPassArgs A) {
   __shared__ typename Sh::Elem lds[Sh::LDS_N];
   __shared__ double red[NT / 64 + 1];
   reduce_prev_shifts(A, (int64_t)blockIdx.x * (NT / 64), (int64_t)gridDim.x * (NT / 64));
-  colpass_tiles<T, NT, RB, NH, CB, QM, SPLIT, true, true>(A, blockIdx.x, gridDim.x, lds, red);
+  colpass_tiles<T, NT, RB, NH, CB, QM, SPLIT, true, true, true>(A, blockIdx.x, gridDim.x, lds, red);
 }
 
 // Backward row pass: rows of 2^NL adjoint values, read in the row pass's output layout (register

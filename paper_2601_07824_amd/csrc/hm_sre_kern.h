@@ -87,8 +87,12 @@ struct StateTileArgs {
         qa(qa_) {}
 };
 
-// Row tiles t0, t0 + tstep, ... < A.n_tiles.
-template <typename T, int NT, int RB, int NL, bool WRITE, int QM, bool SPLIT, typename Args = RowPassArgs>
+// Row tiles t0, t0 + tstep, ... < A.n_tiles; ONE: the tile t0 only (launches of one workgroup per
+// tile).  Without the loop the compiler does not keep every fold case's addresses live across
+// tiles: the tile needs far fewer registers (measured at n = 12: 162 -> 98 VGPRs, 18.6 -> 12.6 us
+// per launch on MI355X).
+template <typename T, int NT, int RB, int NL, bool WRITE, int QM, bool SPLIT, typename Args = RowPassArgs,
+          bool ONE = false>
 __device__ __forceinline__ void rowpass_tiles(const Args &A, int64_t t0, int64_t tstep,
                                               typename RowShape<T, NT, RB, NL, SPLIT>::Elem *lds, double *red,
                                               uint32_t tau = threadIdx.x) {
@@ -187,6 +191,7 @@ __device__ __forceinline__ void rowpass_tiles(const Args &A, int64_t t0, int64_t
         for (int k = 0; k < A.nacc; ++k) o[k] = bad ? __builtin_nan("") : s[k];
       }
     }
+    if constexpr (ONE) break;
   }
 }
 
@@ -195,12 +200,13 @@ __device__ __forceinline__ void rowpass_tiles(const Args &A, int64_t t0, int64_t
 template <typename T, bool SPLIT>
 struct TwoPassWaves { static constexpr int value = (SPLIT && sizeof(T) == 4) ? 4 : 1; };
 
+// One workgroup per tile (grid = n_tiles).
 template <typename T, int NT, int RB, int NL, bool WRITE, int QM, bool SPLIT = false>
 __global__ __launch_bounds__(NT, (WRITE ? TwoPassWaves<T, SPLIT>::value : 1)) void k_sre_rowpass(RowPassArgs A) {
   using Sh = RowShape<T, NT, RB, NL, SPLIT>;
   __shared__ typename Sh::Elem lds[Sh::LDS_N];
   __shared__ double red[NT / 64 + 1];
-  rowpass_tiles<T, NT, RB, NL, WRITE, QM, SPLIT>(A, blockIdx.x, gridDim.x, lds, red);
+  rowpass_tiles<T, NT, RB, NL, WRITE, QM, SPLIT, RowPassArgs, true>(A, blockIdx.x, gridDim.x, lds, red);
 }
 
 // The same with a register budget for at least MINW waves per SIMD (resident tiles of <= 2^13
@@ -210,7 +216,7 @@ __global__ __launch_bounds__(NT, MINW) void k_sre_rowpass_occ(RowPassArgs A) {
   using Sh = RowShape<T, NT, RB, NL, true>;
   __shared__ typename Sh::Elem lds[Sh::LDS_N];
   __shared__ double red[NT / 64 + 1];
-  rowpass_tiles<T, NT, RB, NL, false, QM, true>(A, blockIdx.x, gridDim.x, lds, red);
+  rowpass_tiles<T, NT, RB, NL, false, QM, true, RowPassArgs, true>(A, blockIdx.x, gridDim.x, lds, red);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -293,7 +299,8 @@ struct ColShape {
 // column stages run again in reverse order (the transform is its own adjoint) and the tile is
 // written back in place.
 // XCD: tiles t0, t0 + tstep, ... are taken through xcd_tile (tstep a multiple of 8).
-template <typename T, int NT, int RB, int NH, int CB, int QM, bool SPLIT, bool ADJ = false, bool XCD = false>
+template <typename T, int NT, int RB, int NH, int CB, int QM, bool SPLIT, bool ADJ = false, bool XCD = false,
+          bool ONE = false>
 __device__ __forceinline__ void colpass_tiles(const ColPassArgs &A, int64_t t0, int64_t tstep,
                                               typename ColShape<T, NT, RB, NH, CB, SPLIT>::Elem *lds, double *red) {
   constexpr int R = 1 << RB;
@@ -390,6 +397,7 @@ __device__ __forceinline__ void colpass_tiles(const ColPassArgs &A, int64_t t0, 
         st32(exw, base + (row << A.nl), v);
       }
     }
+    if constexpr (ONE) break;
   }
 }
 
@@ -399,7 +407,7 @@ __global__ __launch_bounds__(NT) void k_sre_colpass(ColPassArgs A) {
   __shared__ typename Sh::Elem lds[Sh::LDS_N];
   __shared__ double red[NT / 64 + 1];
   reduce_prev_shifts(A, (int64_t)blockIdx.x * (NT / 64), (int64_t)gridDim.x * (NT / 64));
-  colpass_tiles<T, NT, RB, NH, CB, QM, SPLIT, false, true>(A, blockIdx.x, gridDim.x, lds, red);
+  colpass_tiles<T, NT, RB, NH, CB, QM, SPLIT, false, true, true>(A, blockIdx.x, gridDim.x, lds, red);
 }
 
 // per-shift sums from column-pass partials of the last batch: one wave per shift (launch
@@ -419,7 +427,9 @@ static inline unsigned shift_reduce_grid(int64_t n_slots) {
 
 static inline int nacc_of(const QArgs &qa) { return qa.nq + 1; }
 static inline bool is_q2(const QArgs &qa) { return qa.nq == 1 && qa.q[0] == 2.0; }
-static inline int64_t grid_for(int64_t tiles) { return tiles < 65536 ? tiles : 65536; }
+// One workgroup per tile: the row and column kernels take tile blockIdx.x only.  (Tile counts stay
+// far below 2^31: at most batch x 2^nh row tasks of a launch.)
+static inline int64_t grid_for(int64_t tiles) { return tiles; }
 
 // Register-tile bits of the workgroup-resident kernels (values per thread = 2^RB).
 template <typename T> struct ResidentRB;
@@ -451,7 +461,8 @@ static void launch_row_occ(const RowPassArgs &A, bool q2, hipStream_t st) {
 }
 
 // split: tiles of 2^10..2^14 (FP32) / 2^10..2^13 (FP64) values use split LDS staging and a register
-// budget of 3 waves per SIMD (4 for 2^14 FP32 values: 512 threads x 32 values in 128 registers).
+// budget of at least 3 waves per SIMD (4 for 2^14 FP32 values: 512 threads x 32 values in 128
+// registers); one tile per workgroup, the tiles use about 100 registers.
 template <typename T>
 static int launch_resident(int NL, RowPassArgs A, bool q2, hipStream_t st, bool split = false) {
   constexpr int RB = ResidentRB<T>::value;
@@ -462,9 +473,11 @@ static int launch_resident(int NL, RowPassArgs A, bool q2, hipStream_t st, bool 
     launch_row_occ<T, nt, RB, nl, w>(A, q2, st);                    \
     return OK;
     if constexpr (RB == 5) {
-      switch (NL) { HM_RO(10, 128, 3) HM_RO(11, 128, 3) HM_RO(12, 128, 3) HM_RO(13, 256, 3) HM_RO(14, 512, 4) default: break; }
+      // one shift per workgroup from 2^11 values on (a one-wave workgroup at 2^11: measured 18.6 ->
+      // 12.6 us at n = 12 against two shifts per 128-thread workgroup)
+      switch (NL) { HM_RO(10, 64, 3) HM_RO(11, 64, 3) HM_RO(12, 128, 3) HM_RO(13, 256, 3) HM_RO(14, 512, 4) default: break; }
     } else {
-      switch (NL) { HM_RO(10, 128, 3) HM_RO(11, 128, 3) HM_RO(12, 256, 3) HM_RO(13, 512, 3) default: break; }
+      switch (NL) { HM_RO(10, 64, 3) HM_RO(11, 128, 3) HM_RO(12, 256, 3) HM_RO(13, 512, 3) default: break; }
     }
 #undef HM_RO
   }
