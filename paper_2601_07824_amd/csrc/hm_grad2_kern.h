@@ -23,8 +23,8 @@ __global__ __launch_bounds__(NT) void k_sre_colpass_adj(ColPassArgs A) {
   using Sh = ColShape<T, NT, RB, NH, CB, SPLIT>;
   __shared__ typename Sh::Elem lds[Sh::LDS_N];
   __shared__ double red[NT / 64 + 1];
-  reduce_prev_shifts(A, (int64_t)blockIdx.x * (NT / 64), (int64_t)gridDim.x * (NT / 64));
-  colpass_tiles<T, NT, RB, NH, CB, QM, SPLIT, true, true, true>(A, blockIdx.x, gridDim.x, lds, red);
+  if (A.tile0 == 0) reduce_prev_shifts(A, (int64_t)blockIdx.x * (NT / 64), (int64_t)gridDim.x * (NT / 64));
+  colpass_tiles<T, NT, RB, NH, CB, QM, SPLIT, true, true, true>(A, A.tile0 + blockIdx.x, gridDim.x, lds, red);
 }
 
 // Backward row pass: rows of 2^NL adjoint values, read in the row pass's output layout (register
@@ -373,10 +373,12 @@ static void grad2_launch_nf(int step, RowPassArgs &A, ColPassArgs &C, const Fuse
   if (step == 2) {
     C.n_cb = (int64_t)1 << (C.nl - CB);
     C.n_tiles = C.n_slots * C.n_cb;
-    const dim3 grid((unsigned)grid_for(C.n_tiles)), block(NTC);
     ProfScope prof("sre_grad_colpass", st);
-    if (q2) hipLaunchKernelGGL((k_sre_colpass_adj<T, NTC, RBC, NH, CB, 2, SPLIT>), grid, block, 0, st, C);
-    else hipLaunchKernelGGL((k_sre_colpass_adj<T, NTC, RBC, NH, CB, 0, SPLIT>), grid, block, 0, st, C);
+    for (C.tile0 = 0; C.tile0 < C.n_tiles; C.tile0 += MAX_GRID) {
+      const dim3 grid((unsigned)grid_for(C.n_tiles - C.tile0)), block(NTC);
+      if (q2) hipLaunchKernelGGL((k_sre_colpass_adj<T, NTC, RBC, NH, CB, 2, SPLIT>), grid, block, 0, st, C);
+      else hipLaunchKernelGGL((k_sre_colpass_adj<T, NTC, RBC, NH, CB, 0, SPLIT>), grid, block, 0, st, C);
+    }
   } else if (step == 3) {
     // row tiles of 2^4 values per thread on the row side of the gradient (the plan's row_rb)
     constexpr int RBR = 4;

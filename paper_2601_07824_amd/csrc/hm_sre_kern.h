@@ -48,6 +48,7 @@ struct RowPassArgs {
   double *shift_sums;   // REDUCE: [n_slots][nacc]
   int nacc;
   int64_t n_tiles;
+  int64_t tile0;        // first tile of this launch (launches of one workgroup per tile, in chunks)
   QArgs qa;
   // batched mode (n_states > 0): slot s is shift s mod 2^state_bits of state s >> state_bits
   int n_states;
@@ -206,7 +207,7 @@ __global__ __launch_bounds__(NT, (WRITE ? TwoPassWaves<T, SPLIT>::value : 1)) vo
   using Sh = RowShape<T, NT, RB, NL, SPLIT>;
   __shared__ typename Sh::Elem lds[Sh::LDS_N];
   __shared__ double red[NT / 64 + 1];
-  rowpass_tiles<T, NT, RB, NL, WRITE, QM, SPLIT, RowPassArgs, true>(A, blockIdx.x, gridDim.x, lds, red);
+  rowpass_tiles<T, NT, RB, NL, WRITE, QM, SPLIT, RowPassArgs, true>(A, A.tile0 + blockIdx.x, gridDim.x, lds, red);
 }
 
 // The same with a register budget for at least MINW waves per SIMD (resident tiles of <= 2^13
@@ -216,7 +217,7 @@ __global__ __launch_bounds__(NT, MINW) void k_sre_rowpass_occ(RowPassArgs A) {
   using Sh = RowShape<T, NT, RB, NL, true>;
   __shared__ typename Sh::Elem lds[Sh::LDS_N];
   __shared__ double red[NT / 64 + 1];
-  rowpass_tiles<T, NT, RB, NL, false, QM, true, RowPassArgs, true>(A, blockIdx.x, gridDim.x, lds, red);
+  rowpass_tiles<T, NT, RB, NL, false, QM, true, RowPassArgs, true>(A, A.tile0 + blockIdx.x, gridDim.x, lds, red);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -230,6 +231,7 @@ struct ColPassArgs {
   double *partials;   // [n_slots][n_cb][nacc]
   int nacc;
   int64_t n_tiles;
+  int64_t tile0;      // first tile of this launch (launches of one workgroup per tile, in chunks)
   QArgs qa;
   // per-shift reduction of the previous batch's partials (written by the previous launch)
   const double *prev_partials;
@@ -406,8 +408,8 @@ __global__ __launch_bounds__(NT) void k_sre_colpass(ColPassArgs A) {
   using Sh = ColShape<T, NT, RB, NH, CB, SPLIT>;
   __shared__ typename Sh::Elem lds[Sh::LDS_N];
   __shared__ double red[NT / 64 + 1];
-  reduce_prev_shifts(A, (int64_t)blockIdx.x * (NT / 64), (int64_t)gridDim.x * (NT / 64));
-  colpass_tiles<T, NT, RB, NH, CB, QM, SPLIT, false, true, true>(A, blockIdx.x, gridDim.x, lds, red);
+  if (A.tile0 == 0) reduce_prev_shifts(A, (int64_t)blockIdx.x * (NT / 64), (int64_t)gridDim.x * (NT / 64));
+  colpass_tiles<T, NT, RB, NH, CB, QM, SPLIT, false, true, true>(A, A.tile0 + blockIdx.x, gridDim.x, lds, red);
 }
 
 // per-shift sums from column-pass partials of the last batch: one wave per shift (launch
@@ -427,9 +429,11 @@ static inline unsigned shift_reduce_grid(int64_t n_slots) {
 
 static inline int nacc_of(const QArgs &qa) { return qa.nq + 1; }
 static inline bool is_q2(const QArgs &qa) { return qa.nq == 1 && qa.q[0] == 2.0; }
-// One workgroup per tile: the row and column kernels take tile blockIdx.x only.  (Tile counts stay
-// far below 2^31: at most batch x 2^nh row tasks of a launch.)
-static inline int64_t grid_for(int64_t tiles) { return tiles; }
+// One workgroup per tile: the row and column kernels take tile tile0 + blockIdx.x only, in launches
+// of at most MAX_GRID workgroups (gridDim.x x blockDim.x must stay below 2^32; a multiple of 8, so
+// the XCD of a workgroup is blockIdx.x mod 8 in every chunk).
+static constexpr int64_t MAX_GRID = (int64_t)1 << 21;
+static inline int64_t grid_for(int64_t tiles) { return tiles < MAX_GRID ? tiles : MAX_GRID; }
 
 // Register-tile bits of the workgroup-resident kernels (values per thread = 2^RB).
 template <typename T> struct ResidentRB;
@@ -437,11 +441,13 @@ template <> struct ResidentRB<float> { static constexpr int value = 5; };
 template <> struct ResidentRB<double> { static constexpr int value = 4; };
 
 template <typename T, int NT, int RB, int NL, bool WRITE, bool SPLIT = false>
-static void launch_row_q(const RowPassArgs &A, bool q2, hipStream_t st) {
-  const dim3 grid((unsigned)grid_for(A.n_tiles)), block(NT);
+static void launch_row_q(RowPassArgs A, bool q2, hipStream_t st) {
   ProfScope prof(WRITE ? "sre_rowpass_write" : "sre_rowpass_resident", st);
-  if (WRITE || !q2) hipLaunchKernelGGL((k_sre_rowpass<T, NT, RB, NL, WRITE, 0, SPLIT>), grid, block, 0, st, A);
-  else hipLaunchKernelGGL((k_sre_rowpass<T, NT, RB, NL, WRITE, 2, SPLIT>), grid, block, 0, st, A);
+  for (A.tile0 = 0; A.tile0 < A.n_tiles; A.tile0 += MAX_GRID) {
+    const dim3 grid((unsigned)grid_for(A.n_tiles - A.tile0)), block(NT);
+    if (WRITE || !q2) hipLaunchKernelGGL((k_sre_rowpass<T, NT, RB, NL, WRITE, 0, SPLIT>), grid, block, 0, st, A);
+    else hipLaunchKernelGGL((k_sre_rowpass<T, NT, RB, NL, WRITE, 2, SPLIT>), grid, block, 0, st, A);
+  }
 }
 
 template <int NT, int RB, int NL>
@@ -453,11 +459,13 @@ static int64_t row_tiles(const RowPassArgs &A) {
 
 // Workgroup-resident row pass (one row = one whole folded shift vector of 2^NL values).
 template <typename T, int NT, int RB, int NL, int MINW>
-static void launch_row_occ(const RowPassArgs &A, bool q2, hipStream_t st) {
-  const dim3 grid((unsigned)grid_for(A.n_tiles)), block(NT);
+static void launch_row_occ(RowPassArgs A, bool q2, hipStream_t st) {
   ProfScope prof("sre_rowpass_resident", st);
-  if (q2) hipLaunchKernelGGL((k_sre_rowpass_occ<T, NT, RB, NL, 2, MINW>), grid, block, 0, st, A);
-  else hipLaunchKernelGGL((k_sre_rowpass_occ<T, NT, RB, NL, 0, (MINW > 3 ? 3 : MINW)>), grid, block, 0, st, A);  // general q: more accumulators
+  for (A.tile0 = 0; A.tile0 < A.n_tiles; A.tile0 += MAX_GRID) {
+    const dim3 grid((unsigned)grid_for(A.n_tiles - A.tile0)), block(NT);
+    if (q2) hipLaunchKernelGGL((k_sre_rowpass_occ<T, NT, RB, NL, 2, MINW>), grid, block, 0, st, A);
+    else hipLaunchKernelGGL((k_sre_rowpass_occ<T, NT, RB, NL, 0, (MINW > 3 ? 3 : MINW)>), grid, block, 0, st, A);  // general q: more accumulators
+  }
 }
 
 // split: tiles of 2^10..2^14 (FP32) / 2^10..2^13 (FP64) values use split LDS staging and a register
@@ -568,10 +576,12 @@ static void launch_col_nh(ColPassArgs A, bool q2, hipStream_t st) {
   constexpr int CB = ilog2c(NT) + RB - NH;
   A.n_cb = (int64_t)1 << (A.nl - CB);
   A.n_tiles = A.n_slots * A.n_cb;
-  const dim3 grid((unsigned)grid_for(A.n_tiles)), block(NT);
   ProfScope prof("sre_colpass", st);
-  if (q2) hipLaunchKernelGGL((k_sre_colpass<T, NT, RB, NH, CB, 2, SPLIT>), grid, block, 0, st, A);
-  else hipLaunchKernelGGL((k_sre_colpass<T, NT, RB, NH, CB, 0, SPLIT>), grid, block, 0, st, A);
+  for (A.tile0 = 0; A.tile0 < A.n_tiles; A.tile0 += MAX_GRID) {  // the first chunk also sums the previous batch
+    const dim3 grid((unsigned)grid_for(A.n_tiles - A.tile0)), block(NT);
+    if (q2) hipLaunchKernelGGL((k_sre_colpass<T, NT, RB, NH, CB, 2, SPLIT>), grid, block, 0, st, A);
+    else hipLaunchKernelGGL((k_sre_colpass<T, NT, RB, NH, CB, 0, SPLIT>), grid, block, 0, st, A);
+  }
 }
 
 // Column tiles of 2^col_tb values (col_tb - rb thread bits), RB register bits.

@@ -112,6 +112,22 @@ def test_persistent_launch_equals_per_size_launches(hm, c64):
     np.testing.assert_allclose(a[:, :2], b[:, :2], rtol=(2e-6 if c64 else 1e-12), atol=0)
 
 
+def test_per_size_launch_beyond_one_grid(hm):
+    """A size class whose row tiles outnumber one launch's grid (64 states at n = 16: 4.2e6
+    one-shift tiles > 2^21 workgroups) runs in several chunked launches; the per-class form equals
+    the persistent launch and single calls."""
+    xs = [gpu_state(S.gaussian_state(16, seed=7400 + i), True)[0] for i in range(64)]
+    per = hm.Context()
+    per.set_option(hm.OPT_BATCH_LAUNCH, 2)
+    say("[batched chunked launches] 64 x n=16 c64")
+    a = hm.sre_batched(xs, (2.0,)).cpu().numpy()
+    b = hm.sre_batched(xs, (2.0,), ctx=per).cpu().numpy()
+    np.testing.assert_allclose(a[:, 0], b[:, 0], rtol=2e-6, atol=0)
+    for i in (0, 17, 63):
+        c = hm.sre(xs[i], (2.0,)).cpu().numpy()
+        np.testing.assert_allclose(b[i, :2], c, rtol=2e-6, atol=1e-9)
+
+
 def test_batched_deterministic(hm):
     xs = [gpu_state(S.gaussian_state(n, seed=7200 + n), True)[0] for n in (7, 11, 11, 15)]
     say("[batched determinism]")
