@@ -233,7 +233,9 @@ hm_status hm_sre_grad(hm_handle h, const void *psi, int n, hm_dtype dtype, doubl
  * arrays of device pointers (the arrays are read during the call and not kept); out (device,
  * 2 * batch doubles) receives {M_q, lost_norm} of state s at out[2 s].  Up to n = 13 (HM_C64) /
  * 12 (HM_C128) each launch covers up to 64 states, one workgroup row per state; above, the
- * two-pass kernels take the states one after another on the shared workspace.  Results equal
+ * two-pass kernels take the states one after another, from n = 15 on in turn on two streams (the
+ * caller's and an internal one, default priority), each with half of the workspace; the call
+ * returns with all work ordered before later work on `stream`.  Results equal
  * hm_sre_grad's up to the order of the FP64 partial sums.  Workspace:
  * hm_workspace_size(HM_OP_SRE_GRAD_BATCHED, count = batch).  batch >= 1. */
 hm_status hm_sre_grad_batched(hm_handle h, const void *const *psis, int n, int batch, hm_dtype dtype,

@@ -54,7 +54,7 @@ def batch_states(n, B, c64, seed):
 
 # (n, complex64, batch): resident sizes (one launch per 64 states, 70 = 64 + 6), and complex64
 # n = 14 / complex128 n = 13, which run the two-pass kernels state after state on one workspace.
-CASES = [(3, False, 2), (6, True, 5), (9, False, 7), (12, True, 64), (12, False, 9), (13, True, 70), (14, True, 3),
+CASES = [(3, False, 2), (6, True, 5), (9, False, 7), (12, True, 64), (12, False, 9), (13, True, 70), (14, True, 3), (15, True, 3),
          (13, False, 3)]
 
 
