@@ -166,13 +166,29 @@ __device__ __forceinline__ void rowpass_tiles(const Args &A, int64_t t0, int64_t
       // column to stay a column), so consecutive lanes write consecutive addresses.
       if (active) {
         vec2<T> *ex = (vec2<T> *)A.exch;
-        const uint32_t ob = ((uint32_t)rt << NL) | tlo;
+        if constexpr (sizeof(T) == 4 && RB == 5) {
+          // 16-byte stores: registers r, r + 1 of thread tlo go to columns 2 c, 2 c + 1 with
+          // c = ((r / 2) << S0) | tlo (another fixed column permutation)
+          float4 *ex4 = (float4 *)A.exch;
+          const uint32_t ob4 = ((uint32_t)rt << (NL - 1)) | tlo;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          vec2<T> v;
-          v.x = re[r];
-          v.y = im[r];
-          st32(ex, ob + ((uint32_t)r << S0), v);
+          for (int r = 0; r < R; r += 2) {
+            float4 v;
+            v.x = re[r];
+            v.y = im[r];
+            v.z = re[r + 1];
+            v.w = im[r + 1];
+            st32(ex4, ob4 + ((uint32_t)(r >> 1) << S0), v);
+          }
+        } else {
+          const uint32_t ob = ((uint32_t)rt << NL) | tlo;
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            vec2<T> v;
+            v.x = re[r];
+            v.y = im[r];
+            st32(ex, ob + ((uint32_t)r << S0), v);
+          }
         }
       }
     } else {
