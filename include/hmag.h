@@ -25,7 +25,10 @@
  *     launched and the outputs are untouched.  The detailed message of the last error on the calling
  *     thread is available from hm_last_error().
  *   - The state is not renormalised (S_q scales as |psi|^{4q}); lost_norm reports 1 - sum_P <P>^2/2^N.
- *   - Results are bitwise reproducible for a fixed (entry point, n, dtype, q list, library build).
+ *   - Results are bitwise reproducible for a fixed (entry point, n, dtype, q list, launch plan,
+ *     library build): every reduction runs in a fixed order.  The plan is the handle's options or
+ *     its autotuned choice; another plan (e.g. other row bits) changes the FP32 rounding of the
+ *     transforms, and with it the last bits of the result.
  *   - Floating point: HM_C128 runs the transforms and sums in FP64.  HM_C64 runs the transforms in
  *     FP32 and accumulates every sum over Pauli strings / phase-space points in FP64 (each thread
  *     sums at most 64 FP32 terms before widening).
