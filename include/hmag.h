@@ -245,6 +245,19 @@ hm_status hm_sre_grad_batched(hm_handle h, const void *const *psis, int n, int b
                               double q, double *out, void *const *grads, void *ws, size_t ws_bytes,
                               hipStream_t stream);
 
+/* hm_sre_grad for `batch` states of uneven n (one q): psis, grads: HOST arrays of `batch` DEVICE
+ * pointers, ns: HOST array of their n (1..20).  Consecutive states of equal n form one batched
+ * gradient (hm_sre_grad_batched) each, so a batch ordered by n is taken in the fewest runs; the
+ * runs share the workspace in stream order.  out (device, 2 * batch doubles) receives {M_q, lost_norm}
+ * of state s at out[2 s]; grads[s] as hm_sre_grad's grad (same dtype and length as psis[s]).
+ * Workspace: hm_sre_batched_grad_workspace (the largest run's).  This is the gradient of the batched
+ * form of Algorithm 2 (the X-string loop of every state in independent chunks, Sec. "Calculation of
+ * SRE for qubits"), differentiated as for hm_sre_grad. */
+hm_status hm_sre_batched_grad_workspace(hm_handle h, const int *ns, int batch, hm_dtype dtype, size_t *bytes);
+hm_status hm_sre_batched_grad(hm_handle h, const void *const *psis, const int *ns, int batch, hm_dtype dtype,
+                              double q, double *out, void *const *grads, void *ws, size_t ws_bytes,
+                              hipStream_t stream);
+
 /* Many states, each of its own qubit count, in one call (all of one dtype and one q list): the
  * batched form of Algorithm 2 (every X-shift of every state is an independent transform; the
  * chunks of the X-string loop that Sec. "Calculation of SRE for qubits" evaluates separately).

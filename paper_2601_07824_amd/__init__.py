@@ -18,7 +18,7 @@ from typing import Sequence
 
 __all__ = [
     "HmError", "lib", "lib_path", "Context", "default_context", "sre", "sre_partial", "sre_finalize",
-    "sre_rows", "sre_row_values", "sre_noalloc", "sre_mc", "McParams", "mc_random_inputs", "sre_grad", "sre_grad_batched", "SRE", "SREBatched", "sre_batched", "sre_sampled", "autotune", "autotune_mana", "autotune_grad", "autotune_batched", "tuned_plan", "mana", "mana_partial", "mana_mixed", "mana_qudit", "reduced_density_matrix", "workspace_size",
+    "sre_rows", "sre_row_values", "sre_noalloc", "sre_mc", "McParams", "mc_random_inputs", "sre_grad", "sre_grad_batched", "sre_grad_uneven", "SRE", "SREBatched", "sre_batched", "sre_sampled", "autotune", "autotune_mana", "autotune_grad", "autotune_batched", "tuned_plan", "mana", "mana_partial", "mana_mixed", "mana_qudit", "reduced_density_matrix", "workspace_size",
     "HM_C64", "HM_C128", "profile_enable", "profile_reset", "profile_read", "OP_SRE", "OP_SRE_ROWS", "OP_ROW_VALUES", "OP_SRE_GRAD", "OP_MANA",
     "OP_SRE_SAMPLED", "OP_SRE_GRAD_BATCHED", "EXPORTED_SYMBOLS",
 ]
@@ -64,6 +64,9 @@ _SIGS = {
     "hm_mana_mixed": (_i, [_vp, _vp, _i, _i, _vp, _vp, _sz, _vp]),
     "hm_mana_qudit": (_i, [_vp, _vp, _i, _i, _i, _vp, _vp, _sz, _vp]),
     "hm_reduced_density": (_i, [_vp, _vp, _i, _i, _i, _vp, _vp]),
+    "hm_sre_batched_grad_workspace": (_i, [_vp, ctypes.POINTER(_i), _i, _i, ctypes.POINTER(_sz)]),
+    "hm_sre_batched_grad": (_i, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_i), _i, _i, ctypes.c_double, _vp,
+                                 ctypes.POINTER(_vp), _vp, _sz, _vp]),
     "hm_sre_batched_workspace": (_i, [_vp, ctypes.POINTER(_i), _i, _i, _i, ctypes.POINTER(_sz)]),
     "hm_sre_batched": (_i, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_i), _i, _i, _dp, _i, _vp, _vp, _sz, _vp]),
     "hm_sre_sampled": (_i, [_vp, _vp, _i, _i, _vp, _i64, _vp, _vp, _sz, _vp]),
@@ -560,6 +563,35 @@ def sre_grad_batched(states, q: float = 2.0, *, ctx: Context | None = None, stre
     _check(lib().hm_sre_grad_batched(ctx.h, ptrs, n, B, dt, float(q), _ptr(out), gptrs, _ptr(ws), ws.numel(),
                                      _stream(stream)))
     return out, (grads if as_rows else list(grads.unbind(0)))
+
+
+def sre_grad_uneven(states, q: float = 2.0, *, ctx: Context | None = None, stream=None):
+    """hm_sre_batched_grad: fused forward + adjoint of M_q for a list of states of uneven n (one
+    dtype).  Returns (out, grads): out is a (B, 2) float64 tensor of [M_q, lost_norm], grads a list of
+    tensors shaped like the states.  Consecutive states of equal n share one batched launch."""
+    torch = _torch()
+    ctx = ctx or default_context()
+    states = [s for s in states]
+    if not states:
+        raise ValueError("empty batch")
+    checked = [_state(s, 2) for s in states]
+    psis = [c[0] for c in checked]
+    ns = [c[1] for c in checked]
+    dt = _dtype_code(psis[0])
+    if any(_dtype_code(p) != dt for p in psis) or any(p.device != psis[0].device for p in psis):
+        raise TypeError("all states must share one dtype and device")
+    B = len(psis)
+    grads = [torch.empty_like(p) for p in psis]
+    out = torch.empty((B, 2), dtype=torch.float64, device=psis[0].device)
+    ns_a = (_i * B)(*ns)
+    pp = (_vp * B)(*[p.data_ptr() for p in psis])
+    gp = (_vp * B)(*[g.data_ptr() for g in grads])
+    nb = _sz(0)
+    _check(lib().hm_sre_batched_grad_workspace(ctx.h, ns_a, B, dt, ctypes.byref(nb)))
+    ws = _workspace(nb.value, psis[0].device, stream)
+    _check(lib().hm_sre_batched_grad(ctx.h, pp, ns_a, B, dt, float(q), _ptr(out), gp, _ptr(ws), ws.numel(),
+                                     _stream(stream)))
+    return out, grads
 
 
 def _make_autograd():

@@ -7,6 +7,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <utility>
 #include <vector>
 
 #include "../../include/hmag.h"
@@ -384,6 +385,61 @@ hm_status hm_sre_grad_batched(hm_handle h, const void *const *psis, int n, int b
   HM_TRY(check_ws(ws, ws_bytes, need));
   for (int s = 0; s < batch; ++s) HM_TRY(norm_ok(h, psis[s], 2, n, dtype, stream));
   return (hm_status)sre_grad_batched_launch(o, n, dtype == HM_C128, psis, batch, q, out, grads, ws, ws_bytes, stream);
+}
+
+// Runs [i0, i1) of consecutive states with equal n (batches of uneven n: one batched gradient per run).
+static void equal_n_runs(const int *ns, int batch, std::vector<std::pair<int, int>> *runs) {
+  for (int i0 = 0; i0 < batch;) {
+    int i1 = i0 + 1;
+    while (i1 < batch && ns[i1] == ns[i0]) ++i1;
+    runs->push_back({i0, i1});
+    i0 = i1;
+  }
+}
+
+hm_status hm_sre_batched_grad_workspace(hm_handle h, const int *ns, int batch, hm_dtype dtype, size_t *bytes) {
+  g_err[0] = 0;
+  if (!h || !ns || !bytes) return (hm_status)fail(E_ARG, "h, ns or bytes is NULL");
+  HM_TRY(check_dtype(dtype));
+  if (batch < 1) return (hm_status)fail(E_ARG, "gradient: batch = %d < 1", batch);
+  std::vector<std::pair<int, int>> runs;
+  equal_n_runs(ns, batch, &runs);
+  size_t need = 256;
+  for (const auto &r : runs) {
+    const int n = ns[r.first];
+    if (n < 1 || n > 20) return (hm_status)fail(E_SIZE, "gradient: n = %d (state %d) outside [1, 20]", n, r.first);
+    size_t b = 0;
+    HM_TRY(sre_grad_batched_workspace(grad_opts(h, n, dtype == HM_C128), n, dtype == HM_C128, r.second - r.first, &b));
+    if (b > need) need = b;
+  }
+  *bytes = need;
+  return HM_OK;
+}
+
+hm_status hm_sre_batched_grad(hm_handle h, const void *const *psis, const int *ns, int batch, hm_dtype dtype, double q,
+                              double *out, void *const *grads, void *ws, size_t ws_bytes, hipStream_t stream) {
+  g_err[0] = 0;
+  if (!h) return (hm_status)fail(E_ARG, "h is NULL");
+  if (!psis || !ns || !grads) return (hm_status)fail(E_ARG, "psis, ns or grads is NULL");
+  size_t need = 0;
+  HM_TRY(hm_sre_batched_grad_workspace(h, ns, batch, dtype, &need));
+  for (int s = 0; s < batch; ++s) {
+    HM_TRY(check_ptr(psis[s], psi_align(dtype), "psis[s]"));
+    HM_TRY(check_ptr(grads[s], psi_align(dtype), "grads[s]"));
+  }
+  HM_TRY(check_ptr(out, 8, "out"));
+  if (!(q > 0.0) || !isfinite(q) || q == 1.0) return (hm_status)fail(E_ARG, "gradient: q = %g must be positive, finite and != 1", q);
+  HM_TRY(check_ws(ws, ws_bytes, need));
+  for (int s = 0; s < batch; ++s) HM_TRY(norm_ok(h, psis[s], 2, ns[s], dtype, stream));
+  std::vector<std::pair<int, int>> runs;
+  equal_n_runs(ns, batch, &runs);
+  for (const auto &r : runs) {  // the runs share the workspace in stream order
+    const int n = ns[r.first];
+    HM_TRY(sre_grad_batched_launch(grad_opts(h, n, dtype == HM_C128), n, dtype == HM_C128, psis + r.first,
+                                   r.second - r.first, q, out + 2 * (size_t)r.first, grads + r.first, ws, ws_bytes,
+                                   stream));
+  }
+  return HM_OK;
 }
 
 // Default launch form of the batched forward (HM_OPT_BATCH_LAUNCH).

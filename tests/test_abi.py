@@ -405,3 +405,20 @@ def test_long_row_plans(L, h):
             assert L.hm_workspace_size(hh, 0, 24, dt, 1, 0, ctypes.byref(b)) == want, (rb, dt, split)
     finally:
         L.hm_destroy(hh)
+
+
+def test_batched_grad_uneven_argument_errors(L, h):
+    good, ws = P(0x100000), P(0x200000)
+    b = ctypes.c_size_t(0)
+    ns = (ctypes.c_int * 4)(8, 8, 13, 9)
+    assert L.hm_sre_batched_grad_workspace(h, ns, 4, 0, ctypes.byref(b)) == HM_OK and b.value >= 256
+    bad = (ctypes.c_int * 2)(8, 21)
+    assert L.hm_sre_batched_grad_workspace(h, bad, 2, 0, ctypes.byref(b)) == HM_E_SIZE
+    assert L.hm_sre_batched_grad_workspace(h, ns, 0, 0, ctypes.byref(b)) == HM_E_ARG
+    assert L.hm_sre_batched_grad_workspace(h, ns, 4, 2, ctypes.byref(b)) == HM_E_DTYPE
+    psis = (ctypes.c_void_p * 4)(good, good, good, good)
+    grads = (ctypes.c_void_p * 4)(ws, ws, ws, ws)
+    assert L.hm_sre_batched_grad(h, None, ns, 4, 0, 2.0, good, grads, ws, 1 << 30, None) == HM_E_ARG
+    assert L.hm_sre_batched_grad(h, psis, ns, 4, 0, 1.0, good, grads, ws, 1 << 30, None) == HM_E_ARG
+    assert L.hm_sre_batched_grad(h, psis, ns, 4, 0, 2.0, None, grads, ws, 1 << 30, None) == HM_E_ARG
+    assert L.hm_sre_batched_grad(h, psis, ns, 4, 0, 2.0, good, grads, ws, 64, None) == HM_E_WORKSPACE

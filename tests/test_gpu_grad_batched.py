@@ -140,3 +140,21 @@ def test_batch_of_one_is_the_single_call(hm, n, c64):
     o1, g1 = hm.sre_grad(X[0], 2.0)
     assert np.array_equal(out[0].cpu().numpy(), o1.cpu().numpy())
     assert np.array_equal(G[0].cpu().numpy(), g1.cpu().numpy())
+
+
+@pytest.mark.parametrize("c64", [True, False])
+def test_grad_uneven_sizes_vs_single_calls(hm, c64):
+    """hm_sre_batched_grad on a batch of uneven n (runs of equal n share a batched launch; resident and
+    two-pass sizes, a two-lane run at n = 15) against one hm_sre_grad call per state."""
+    ns = [8, 8, 12, 13, 13, 9, 15, 15, 6] if c64 else [8, 8, 11, 12, 13, 9, 6]
+    X = [torch.from_numpy(S.gaussian_state(n, seed=7600 + i)).to(torch.complex64 if c64 else torch.complex128).cuda()
+         for i, n in enumerate(ns)]
+    say(f"[grad uneven] c64={c64} ns={ns}")
+    out, G = hm.sre_grad_uneven(X, 2.0)
+    torch.cuda.synchronize()
+    out = out.cpu().numpy()
+    tol = 1e-5 if c64 else 1e-12
+    for i, x in enumerate(X):
+        o1, g1 = hm.sre_grad(x, 2.0)
+        assert rel_l2(G[i].cpu().numpy().astype(np.complex128), g1.cpu().numpy().astype(np.complex128)) < tol, i
+        np.testing.assert_allclose(out[i], o1.cpu().numpy(), rtol=tol, atol=tol)
