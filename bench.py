@@ -25,7 +25,10 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-LANE_OPS_PER_S = 256 * 64 * 2.4e9  # VALU lane operations per second (no packed FP32): 39.3e12
+# FP32 VALU lane operations per second without packed FP32: the vector peak of 157.3 TFLOP/s counts
+# an FMA as 2 FLOP, i.e. 78.6e12 lane-FMAs/s = 2 wave64 instructions per CU per cycle at 2.4 GHz
+# (a plain loop of FP32 adds measured 57e12 adds/s on MI355X, above one instruction per CU-cycle).
+LANE_OPS_PER_S = 2 * 256 * 64 * 2.4e9
 
 
 def sre_kernel_mix(N: int, family: str, nl: int, nh: int):
@@ -76,7 +79,7 @@ def roofline(fam: str, N: int, vals_per_launch: float, t_launch: float, launches
                   "note": "achieved = exchange bytes (8 B per folded value per pass) / average launch time"})
     elif valu:
         r.update({"bound": "alu", **valu, "traffic": traffic_for(fam, f"sre_n{N}_c64", plan),
-                  "note": "FP32 VALU without packed FP32: 39.3e12 lane-ops/s x flops per op of this kernel"})
+                  "note": "FP32 VALU without packed FP32: 78.6e12 lane-ops/s x flops per op of this kernel"})
     return r
 
 
