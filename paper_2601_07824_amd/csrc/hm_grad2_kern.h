@@ -109,8 +109,12 @@ struct FusedArgs {
 
 // RBW: register tile of the row pass that wrote the exchange (its column permutation: row position
 // P sits at column (P mod 2^RBW) 2^(NL-RBW) + P / 2^RBW).  RB <= RBW is this kernel's own tile.
+// Waves per SIMD the fused kernel is compiled for: four (at most 128 VGPRs) for 2^3-value FP32
+// tiles, the grid's own depth at the gradient's largest batches; one otherwise.
+constexpr int fused_waves(int rb, int tbytes) { return (tbytes << rb) <= 32 ? 4 : 1; }
+
 template <typename T, int NT, int RB, int RBW, int NL, bool SPLIT>
-__global__ __launch_bounds__(NT) void k_grad_rowback_accum(FusedArgs F) {
+__global__ __launch_bounds__(NT, fused_waves(RB, sizeof(T))) void k_grad_rowback_accum(FusedArgs F) {
   using Sh = RowShape<T, NT, RB, NL, SPLIT>;
   constexpr int R = 1 << RB;
   constexpr int LT = ilog2c(NT);
@@ -147,55 +151,118 @@ __global__ __launch_bounds__(NT) void k_grad_rowback_accum(FusedArgs F) {
 #pragma unroll
   for (int r = 0; r < R; ++r) axr[r] = axi[r] = T(0);
 
-  for (int64_t sb = s_lo; sb < s_hi; sb += G) {
-    const int64_t s = sb + g;
-    const bool active = s < s_hi;
-    static_assert(RB <= RBW && RBW <= NL, "reader tile within the writer's");
+  static_assert(RB <= RBW && RBW <= NL, "reader tile within the writer's");
+  // Adjoint row of shift slot s in this kernel's layout S = 0: register r of thread tlo holds row
+  // position P = r + R tlo, which the forward row pass stored at column
+  // (P mod 2^RBW) 2^(NL-RBW) + P / 2^RBW.
+  auto load_row = [&](int64_t s, T(&xr)[R], T(&xi)[R]) {
     const uint32_t ob = (((uint32_t)s << F.nh) + ch) << NL;
-    T re[R], im[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      // layout S = 0 of this kernel: register r of thread tlo holds row position r + R tlo
       const uint32_t P = (uint32_t)r + (tlo << RB);
       const uint32_t col = ((P & ((1u << RBW) - 1u)) << (NL - RBW)) | (P >> RBW);
-      vec2<T> v{T(0), T(0)};
-      if (active) v = ld32(ex, ob + col);
-      re[r] = v.x;
-      im[r] = v.y;
+      const vec2<T> v = ld32(ex, ob + col);
+      xr[r] = v.x;
+      xi[r] = v.y;
     }
+  };
+  auto backward_stages = [&](T(&xr)[R], T(&xi)[R]) {
     if constexpr (K >= 4) {
-      wht_regs<T, R, 0, rp_H(NL, RB, 3)>(re, im);
-      if constexpr (SPLIT) relayout_split<T, R, RB, rp_S(NL, RB, 3), rp_S(NL, RB, 2)>(re, im, lds, tau);
-      else relayout<T, R, RB, rp_S(NL, RB, 3), rp_S(NL, RB, 2)>(re, im, lds, tau);
+      wht_regs<T, R, 0, rp_H(NL, RB, 3)>(xr, xi);
+      if constexpr (SPLIT) relayout_split<T, R, RB, rp_S(NL, RB, 3), rp_S(NL, RB, 2)>(xr, xi, lds, tau);
+      else relayout<T, R, RB, rp_S(NL, RB, 3), rp_S(NL, RB, 2)>(xr, xi, lds, tau);
     }
     if constexpr (K >= 3) {
-      wht_regs<T, R, 0, rp_H(NL, RB, 2)>(re, im);
-      if constexpr (SPLIT) relayout_split<T, R, RB, rp_S(NL, RB, 2), rp_S(NL, RB, 1)>(re, im, lds, tau);
-      else relayout<T, R, RB, rp_S(NL, RB, 2), rp_S(NL, RB, 1)>(re, im, lds, tau);
+      wht_regs<T, R, 0, rp_H(NL, RB, 2)>(xr, xi);
+      if constexpr (SPLIT) relayout_split<T, R, RB, rp_S(NL, RB, 2), rp_S(NL, RB, 1)>(xr, xi, lds, tau);
+      else relayout<T, R, RB, rp_S(NL, RB, 2), rp_S(NL, RB, 1)>(xr, xi, lds, tau);
     }
-    wht_regs<T, R, 0, rp_H(NL, RB, 1)>(re, im);
-    if constexpr (SPLIT) relayout_split<T, R, RB, rp_S(NL, RB, 1), rp_S(NL, RB, 0)>(re, im, lds, tau);
-    else relayout<T, R, RB, rp_S(NL, RB, 1), rp_S(NL, RB, 0)>(re, im, lds, tau);
-    wht_regs<T, R, 0, rp_H(NL, RB, 0)>(re, im);
-    if (active) {
-      const uint32_t a = (uint32_t)(F.a0 + (uint64_t)s);
-      const uint32_t m = jhi ? (a & (uint32_t)(ROW - 1)) : (a & ((1u << j) - 1u));  // partner position = p ^ m
-      vec2<T> *sl = slice + g * ROW;
+    wht_regs<T, R, 0, rp_H(NL, RB, 1)>(xr, xi);
+    if constexpr (SPLIT) relayout_split<T, R, RB, rp_S(NL, RB, 1), rp_S(NL, RB, 0)>(xr, xi, lds, tau);
+    else relayout<T, R, RB, rp_S(NL, RB, 1), rp_S(NL, RB, 0)>(xr, xi, lds, tau);
+    wht_regs<T, R, 0, rp_H(NL, RB, 0)>(xr, xi);
+  };
+  // x-side gradient entry of register r (after the stages: row position p = tlo + r 2^S0); it does
+  // not depend on the shift
+  auto xpos = [&](int r) -> uint32_t {
+    const uint32_t p = tlo + ((uint32_t)r << S0);
+    return jhi ? ((xh << NL) | p) : ((ch << (NL + 1)) | ins0_32(p, j));
+  };
+  // With 2^3-value FP32 tiles (32 B per register array) the x-side state values stay in registers
+  // for the whole loop, the next shift's row is loaded during the current shift's stages, and the
+  // partner-side state values are gathered together, within 128 VGPRs.  Larger tiles keep the
+  // per-value form (the same arrays would need more than 256 VGPRs).
+  constexpr bool PF = R * sizeof(T) <= 32;
+  if constexpr (PF) {
+    if (s_lo < s_hi) {  // uniform
+      const int64_t s_last = s_hi - 1;
+      T re[R], im[R];
+      vec2<T> px[R];
+      // row tasks past the group's last shift load that shift's row (valid data, not accumulated)
+      load_row((s_lo + g) < s_last ? (s_lo + g) : s_last, re, im);
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const uint32_t p = tlo + ((uint32_t)r << S0);
-        const uint32_t x = jhi ? ((xh << NL) | p) : ((ch << (NL + 1)) | ins0_32(p, j));
-        const uint32_t xp = x ^ a;
-        const vec2<T> py = ld32(psi, xp), px = ld32(psi, x);
-        const T zr = q4 * re[r], zi = q4 * im[r];
-        // G_x += 4q psi_{x^a} Z ;  G_{x^a} += 4q psi_x conj(Z)
-        axr[r] += fmaT(py.x, zr, -(py.y * zi));
-        axi[r] += fmaT(py.x, zi, py.y * zr);
-        vec2<T> o = sl[p ^ m];
-        o.x += fmaT(px.x, zr, px.y * zi);
-        o.y += fmaT(px.y, zr, -(px.x * zi));
-        sl[p ^ m] = o;
-        if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // keep the state gathers in groups of four
+      for (int r = 0; r < R; ++r) px[r] = ld32(psi, xpos(r));
+      for (int64_t sb = s_lo; sb < s_hi; sb += G) {
+        const int64_t s = sb + g;
+        const bool active = s < s_hi;
+        const uint32_t a = (uint32_t)(F.a0 + (uint64_t)(active ? s : s_last));
+        // next row (past the end: the last shift's row again, an L2 hit; no branch, so that the
+        // loads stay in flight through the stages)
+        T nre[R], nim[R];
+        load_row((s + G) < s_last ? (s + G) : s_last, nre, nim);
+        backward_stages(re, im);
+        if (active) {
+          const uint32_t m = jhi ? (a & (uint32_t)(ROW - 1)) : (a & ((1u << j) - 1u));  // partner position = p ^ m
+          vec2<T> *sl = slice + g * ROW;
+          vec2<T> py[R], o[R];
+#pragma unroll
+          for (int r = 0; r < R; ++r) py[r] = ld32(psi, xpos(r) ^ a);
+#pragma unroll
+          for (int r = 0; r < R; ++r) o[r] = sl[(tlo + ((uint32_t)r << S0)) ^ m];
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const T zr = q4 * re[r], zi = q4 * im[r];
+            // G_x += 4q psi_{x^a} Z ;  G_{x^a} += 4q psi_x conj(Z)
+            axr[r] += fmaT(py[r].x, zr, -(py[r].y * zi));
+            axi[r] += fmaT(py[r].x, zi, py[r].y * zr);
+            o[r].x += fmaT(px[r].x, zr, px[r].y * zi);
+            o[r].y += fmaT(px[r].y, zr, -(px[r].x * zi));
+          }
+#pragma unroll
+          for (int r = 0; r < R; ++r) sl[(tlo + ((uint32_t)r << S0)) ^ m] = o[r];
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          re[r] = nre[r];
+          im[r] = nim[r];
+        }
+      }
+    }
+  } else {
+    for (int64_t sb = s_lo; sb < s_hi; sb += G) {
+      const int64_t s = sb + g;
+      const bool active = s < s_hi;
+      T re[R], im[R];
+      load_row(active ? s : s_hi - 1, re, im);
+      backward_stages(re, im);
+      if (active) {
+        const uint32_t a = (uint32_t)(F.a0 + (uint64_t)s);
+        const uint32_t m = jhi ? (a & (uint32_t)(ROW - 1)) : (a & ((1u << j) - 1u));
+        vec2<T> *sl = slice + g * ROW;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const uint32_t p = tlo + ((uint32_t)r << S0);
+          const uint32_t x = xpos(r);
+          const vec2<T> py = ld32(psi, x ^ a), px = ld32(psi, x);
+          const T zr = q4 * re[r], zi = q4 * im[r];
+          axr[r] += fmaT(py.x, zr, -(py.y * zi));
+          axi[r] += fmaT(py.x, zi, py.y * zr);
+          vec2<T> o = sl[p ^ m];
+          o.x += fmaT(px.x, zr, px.y * zi);
+          o.y += fmaT(px.y, zr, -(px.x * zi));
+          sl[p ^ m] = o;
+          if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // keep the state gathers in groups of four
+        }
       }
     }
   }
@@ -355,6 +422,10 @@ __global__ void k_zero2(double2 *p, int64_t n) {
 // 2^8 and 2^9 (half the registers of 2^4, so twice the waves; measured faster there), 2^4 otherwise
 // (rows of 2^10 would need a fourth round).
 constexpr int fused_rb(int nl) { return nl == 8 || nl == 9 ? 3 : 4; }
+// Workgroup size of the fused kernel: 256 threads for 2^3-value FP32 tiles (twice the shifts in
+// flight per workgroup; the launch then uses half as many shift groups, so the waves in flight stay
+// the same and the FP64 partials of G read and written per launch halve), 128 otherwise.
+constexpr int fused_nt(int nl, int tbytes) { return (tbytes << fused_rb(nl)) <= 32 ? 256 : 128; }
 // Register tile of the gradient's forward row pass (the plan's row_rb), which fixes the exchange's
 // column permutation.
 constexpr int GRAD_ROW_RB = 4;
@@ -389,10 +460,10 @@ static void grad2_launch_nf(int step, RowPassArgs &A, ColPassArgs &C, const Fuse
     ProfScope prof("sre_grad_rowback", st);
     hipLaunchKernelGGL((k_sre_rowback<T, NTR, RBR, NL, SPLIT>), grid, block, 0, st, A);
   } else {
-    // fused backward rows + accumulation: 128 threads x 2^RBR values, 2^(7 + RBR - NL) shifts in
+    // fused backward rows + accumulation: NTF threads x 2^RBR values, NTF 2^RBR / 2^NL shifts in
     // flight
     constexpr int RBR = fused_rb(NL);
-    constexpr int NTF = 128;
+    constexpr int NTF = fused_nt(NL, sizeof(T));
     static_assert(ilog2c(NTF) + RBR >= NL, "fused tile must hold a whole row");
     const dim3 grid((unsigned)(((int64_t)1 << F->nh) * F->groups)), block(NTF);
     ProfScope prof("sre_grad_rowback_accum", st);
@@ -505,9 +576,11 @@ int grad2_t(const SrePlan &p, const void *psi, double q, double *out, void *grad
       F.j = j0;
       F.ah = (uint32_t)(a_first >> p.nl);
       F.gpart = gpart;
-      // shift groups: at least one round of the 2^(7 + rb - nl) shifts a workgroup holds at a time
-      const int64_t gf = nb >> (7 + fused_rb(p.nl) - p.nl);
-      F.groups = (int)(gf < 1 ? 1 : gf < groups ? gf : groups);
+      // shift groups: at least one round of the shifts a workgroup holds at a time
+      const int64_t gf = nb >> (ilog2c(fused_nt(p.nl, sizeof(T))) + fused_rb(p.nl) - p.nl);
+      const int gdiv = fused_nt(p.nl, sizeof(T)) / 128;
+      const int gcap = groups / gdiv > 0 ? groups / gdiv : 1;
+      F.groups = (int)(gf < 1 ? 1 : gf < gcap ? gf : gcap);
       e = p.split ? grad2_launch<T, true>(nf, 4, A, C, &F, q2, st) : grad2_launch<T, false>(nf, 4, A, C, &F, q2, st);
       if (e) return e;
       prev_s0 = s0;
