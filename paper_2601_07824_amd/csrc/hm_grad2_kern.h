@@ -109,9 +109,10 @@ struct FusedArgs {
 
 // RBW: register tile of the row pass that wrote the exchange (its column permutation: row position
 // P sits at column (P mod 2^RBW) 2^(NL-RBW) + P / 2^RBW).  RB <= RBW is this kernel's own tile.
-// Waves per SIMD the fused kernel is compiled for: four (at most 128 VGPRs) for 2^3-value FP32
-// tiles, the grid's own depth at the gradient's largest batches; one otherwise.
-constexpr int fused_waves(int rb, int tbytes) { return (tbytes << rb) <= 32 ? 4 : 1; }
+// Waves per SIMD the fused kernel is compiled for (the grid's own depth at the gradient's largest
+// batches): FP32 tiles of 2^3 values four (at most 128 VGPRs), of 2^4 values two (at most 256);
+// FP64 tiles one.
+constexpr int fused_waves(int rb, int tbytes) { return tbytes != 4 ? 1 : rb <= 3 ? 4 : 2; }
 
 template <typename T, int NT, int RB, int RBW, int NL, bool SPLIT>
 __global__ __launch_bounds__(NT, fused_waves(RB, sizeof(T))) void k_grad_rowback_accum(FusedArgs F) {
@@ -188,11 +189,11 @@ __global__ __launch_bounds__(NT, fused_waves(RB, sizeof(T))) void k_grad_rowback
     const uint32_t p = tlo + ((uint32_t)r << S0);
     return jhi ? ((xh << NL) | p) : ((ch << (NL + 1)) | ins0_32(p, j));
   };
-  // With 2^3-value FP32 tiles (32 B per register array) the x-side state values stay in registers
-  // for the whole loop, the next shift's row is loaded during the current shift's stages, and the
-  // partner-side state values are gathered together, within 128 VGPRs.  Larger tiles keep the
-  // per-value form (the same arrays would need more than 256 VGPRs).
-  constexpr bool PF = R * sizeof(T) <= 32;
+  // FP32 tiles (at most 64 B per register array): the x-side state values stay in registers for the
+  // whole loop, the next shift's row is loaded during the current shift's stages, and the
+  // partner-side state values are gathered together.  FP64 tiles keep the one-value-at-a-time form
+  // (the pipelined arrays would need more than 256 VGPRs at 2^4 values).
+  constexpr bool PF = sizeof(T) == 4 && R <= 16;
   if constexpr (PF) {
     if (s_lo < s_hi) {  // uniform
       const int64_t s_last = s_hi - 1;
@@ -422,10 +423,10 @@ __global__ void k_zero2(double2 *p, int64_t n) {
 // 2^8 and 2^9 (half the registers of 2^4, so twice the waves; measured faster there), 2^4 otherwise
 // (rows of 2^10 would need a fourth round).
 constexpr int fused_rb(int nl) { return nl == 8 || nl == 9 ? 3 : 4; }
-// Workgroup size of the fused kernel: 256 threads for 2^3-value FP32 tiles (twice the shifts in
-// flight per workgroup; the launch then uses half as many shift groups, so the waves in flight stay
-// the same and the FP64 partials of G read and written per launch halve), 128 otherwise.
-constexpr int fused_nt(int nl, int tbytes) { return (tbytes << fused_rb(nl)) <= 32 ? 256 : 128; }
+// Workgroup size of the fused kernel: 256 threads for FP32 rows of 2^8..2^10 values (twice the
+// shifts in flight per workgroup; the launch then uses half as many shift groups, so the waves in
+// flight stay the same and the FP64 partials of G read and written per launch halve), 128 otherwise.
+constexpr int fused_nt(int nl, int tbytes) { return tbytes == 4 && nl >= 8 && nl <= 10 ? 256 : 128; }
 // Register tile of the gradient's forward row pass (the plan's row_rb), which fixes the exchange's
 // column permutation.
 constexpr int GRAD_ROW_RB = 4;

@@ -245,6 +245,26 @@ def test_grad_maximum_size_identities(hm):
     assert abs(out.cpu().numpy()[0] - m[0]) < 1e-5 * abs(m[0])
 
 
+def test_grad_maximum_size_c64_vs_c128(hm):
+    """n = 20, the largest gradient size (rows of 2^10 values in the fused backward kernel, the
+    software-pipelined FP32 form): the complex64 gradient against the complex128 gradient (FP64
+    transforms, the one-value-at-a-time form) of the same complex64-exact state, element by element
+    in relative L2, and the complex128 gradient against the homogeneity identity."""
+    n = 20
+    psi = S.ry_rz_cz_state(n, np.random.default_rng(6991).uniform(0, 2 * math.pi, (2, 2, n)))
+    v64, w = S.to_c64_exact(psi)
+    say("[grad max size] n=20 c64 vs c128")
+    o64, g64 = hm.sre_grad(torch.from_numpy(v64).to(_dev()), 2.0)
+    x128 = torch.from_numpy(w).to(_dev())
+    o128, g128 = hm.sre_grad(x128, 2.0)
+    ip = torch.vdot(g128, x128).item()
+    want = 4 * 2.0 / ((1 - 2.0) * math.log(2))
+    assert abs(ip.real - want) < 1e-9 * abs(want) and abs(ip.imag) < 1e-9 * abs(want), ip
+    err = rel_l2(g64.cpu().numpy().astype(np.complex128), g128.cpu().numpy())
+    assert err < 1e-4, err
+    assert abs(o64.cpu().numpy()[0] - o128.cpu().numpy()[0]) < 1e-5 * abs(o128.cpu().numpy()[0])
+
+
 @pytest.mark.parametrize("c64,n,forced", [(False, 5, False), (True, 9, False), (False, 13, True), (True, 14, False)])
 def test_grad_fractional_q(orc, hm, c64, n, forced):
     """q = 1.5 (the general |chi|^{2q-2} chi seed, no integer shortcut) on the resident and two-pass
