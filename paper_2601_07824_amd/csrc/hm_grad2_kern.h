@@ -110,9 +110,9 @@ struct FusedArgs {
 // RBW: register tile of the row pass that wrote the exchange (its column permutation: row position
 // P sits at column (P mod 2^RBW) 2^(NL-RBW) + P / 2^RBW).  RB <= RBW is this kernel's own tile.
 // Waves per SIMD the fused kernel is compiled for (the grid's own depth at the gradient's largest
-// batches): FP32 tiles of 2^3 values four (at most 128 VGPRs), of 2^4 values two (at most 256);
-// FP64 tiles one.
-constexpr int fused_waves(int rb, int tbytes) { return tbytes != 4 ? 1 : rb <= 3 ? 4 : 2; }
+// batches): four (at most 128 VGPRs) for 2^3-value FP32 tiles, two (at most 256) for 2^4-value
+// FP32 and 2^3-value FP64 tiles, one otherwise.
+constexpr int fused_waves(int rb, int tbytes) { return (tbytes << rb) <= 32 ? 4 : (tbytes << rb) <= 64 ? 2 : 1; }
 
 template <typename T, int NT, int RB, int RBW, int NL, bool SPLIT>
 __global__ __launch_bounds__(NT, fused_waves(RB, sizeof(T))) void k_grad_rowback_accum(FusedArgs F) {
@@ -189,11 +189,11 @@ __global__ __launch_bounds__(NT, fused_waves(RB, sizeof(T))) void k_grad_rowback
     const uint32_t p = tlo + ((uint32_t)r << S0);
     return jhi ? ((xh << NL) | p) : ((ch << (NL + 1)) | ins0_32(p, j));
   };
-  // FP32 tiles (at most 64 B per register array): the x-side state values stay in registers for the
-  // whole loop, the next shift's row is loaded during the current shift's stages, and the
-  // partner-side state values are gathered together.  FP64 tiles keep the one-value-at-a-time form
-  // (the pipelined arrays would need more than 256 VGPRs at 2^4 values).
-  constexpr bool PF = sizeof(T) == 4 && R <= 16;
+  // Tiles of at most 64 B per register array (2^3 or 2^4 FP32, 2^3 FP64 values): the x-side state
+  // values stay in registers for the whole loop, the next shift's row is loaded during the current
+  // shift's stages, and the partner-side state values are gathered together.  2^4-value FP64 tiles
+  // keep the one-value-at-a-time form (the pipelined arrays would need more than 256 VGPRs).
+  constexpr bool PF = R * sizeof(T) <= 64;
   if constexpr (PF) {
     if (s_lo < s_hi) {  // uniform
       const int64_t s_last = s_hi - 1;

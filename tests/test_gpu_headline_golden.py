@@ -6,7 +6,7 @@ N = 16 and 18 (two-layer RY/RZ + CZ circuit states) on 4096 seeded entries.
 
 Bounds: complex64 (FP32 transforms, FP64 sums) 1e-5 relative on M and mana; complex128 1e-10.
 Gradients (FP32 transforms): every sampled entry within 1e-4 of the largest gradient entry, and
-relative L2 error over the sample <= 1e-4.  A case whose golden value has not been generated yet
+relative L2 error over the sample <= 1e-4; with complex128 (FP64 transforms, N = 18) 1e-9.  A case whose golden value has not been generated yet
 is skipped with that reason.
 """
 import json
@@ -76,12 +76,15 @@ def test_mana_n12_bench_state(hm, c64):
     np.testing.assert_allclose(got[1:], want[1:], atol=(1e-5 if c64 else 1e-10))
 
 
-@pytest.mark.parametrize("n", [16, 18])
-def test_grad_circuit_states(hm, n):
+@pytest.mark.parametrize("n,c128", [(16, False), (18, False), (18, True)])
+def test_grad_circuit_states(hm, n, c128):
+    """The stored FP64 oracle gradient of the complex64-exact circuit state, against the complex64
+    kernels (FP32 transforms) and, at N = 18, the complex128 kernels on the same values widened."""
     key = f"grad_ryrzcz_n{n}_seed{4000 + n}_c64"
     g = gold(key, "grad_golden.json")
     ang = np.random.default_rng(4000 + n).uniform(0, 2 * math.pi, (2, 2, n))
-    x = torch.from_numpy(S.to_c64_exact(S.ry_rz_cz_state(n, ang))[0]).to(_dev())
+    v64, w = S.to_c64_exact(S.ry_rz_cz_state(n, ang))
+    x = torch.from_numpy(w if c128 else v64).to(_dev())
     out, grad = hm.sre_grad(x, g["q"])
     out = out.cpu().numpy()
     idx = np.asarray(g["idx"], dtype=np.int64)
@@ -91,7 +94,8 @@ def test_grad_circuit_states(hm, n):
     rel_l2 = float(np.linalg.norm(got - want) / np.linalg.norm(want))
     say(f"[headline grad n{n}] M={out[0]:.9f} oracle={g['values'][0]:.9f} max|dg|/|g|inf={d.max() / g['norm_inf']:.2e} "
         f"rel_l2={rel_l2:.2e} |g|_2 gpu={float(torch.linalg.vector_norm(grad).item()):.9f} oracle={g['norm2']:.9f}")
-    assert abs(out[0] - g["values"][0]) <= 1e-5 * abs(g["values"][0])
-    assert np.all(d <= 1e-4 * g["norm_inf"]), d.max()
-    assert rel_l2 <= 1e-4
-    assert abs(float(torch.linalg.vector_norm(grad).item()) - g["norm2"]) <= 1e-4 * g["norm2"]
+    tol = 1e-9 if c128 else 1e-4
+    assert abs(out[0] - g["values"][0]) <= (1e-11 if c128 else 1e-5) * abs(g["values"][0])
+    assert np.all(d <= tol * g["norm_inf"]), d.max()
+    assert rel_l2 <= tol
+    assert abs(float(torch.linalg.vector_norm(grad).item()) - g["norm2"]) <= tol * g["norm2"]
