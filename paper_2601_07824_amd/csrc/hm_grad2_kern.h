@@ -423,10 +423,13 @@ __global__ void k_zero2(double2 *p, int64_t n) {
 // 2^8 and 2^9 (half the registers of 2^4, so twice the waves; measured faster there), 2^4 otherwise
 // (rows of 2^10 would need a fourth round).
 constexpr int fused_rb(int nl) { return nl == 8 || nl == 9 ? 3 : 4; }
-// Workgroup size of the fused kernel: 256 threads for FP32 rows of 2^8..2^10 values (twice the
-// shifts in flight per workgroup; the launch then uses half as many shift groups, so the waves in
-// flight stay the same and the FP64 partials of G read and written per launch halve), 128 otherwise.
-constexpr int fused_nt(int nl, int tbytes) { return tbytes == 4 && nl >= 8 && nl <= 10 ? 256 : 128; }
+// Workgroup size of the fused kernel: 256 threads for FP32 rows of 2^8..2^10 values and FP64 rows of
+// 2^8..2^9 (twice the shifts in flight per workgroup; the launch then uses half as many shift
+// groups, so the waves in flight stay the same and the FP64 partials of G read and written per
+// launch halve), 128 otherwise.
+constexpr int fused_nt(int nl, int tbytes) {
+  return (tbytes == 4 && nl >= 8 && nl <= 10) || (tbytes == 8 && nl >= 8 && nl <= 9) ? 256 : 128;
+}
 // Register tile of the gradient's forward row pass (the plan's row_rb), which fixes the exchange's
 // column permutation.
 constexpr int GRAD_ROW_RB = 4;
