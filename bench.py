@@ -87,22 +87,21 @@ def traffic_for(kernel: str, workload: str, plan: dict | None):
     """HBM/MALL bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE of the committed counter runs,
     each scaled by what the same counter reads for a plain 256 MiB device copy), if the kernel
     sources are unchanged since the counters were taken and the launch configuration is the same;
-    else None."""
+    else None.  A kernel may have one record per measured plan."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path) or not plan:
         return None
     try:
-        rec = json.load(open(path)).get(f"{workload}/{kernel}")
-        if rec is None:
+        recs = json.load(open(path)).get(f"{workload}/{kernel}")
+        if recs is None:
             return None
-        h = hashlib.sha256()
-        for src in rec["sources"]:
-            h.update(open(os.path.join(ROOT, src), "rb").read())
-        if h.hexdigest()[:16] != rec["source_sha"]:
-            return None
-        if any(plan.get(k) != v for k, v in rec["plan"].items()):
-            return None
-        return rec["bytes_per_launch"]
+        for rec in (recs if isinstance(recs, list) else [recs]):  # one record per measured plan
+            h = hashlib.sha256()
+            for src in rec["sources"]:
+                h.update(open(os.path.join(ROOT, src), "rb").read())
+            if h.hexdigest()[:16] == rec["source_sha"] and all(plan.get(k) == v for k, v in rec["plan"].items()):
+                return rec["bytes_per_launch"]
+        return None
     except Exception:
         return None
 
