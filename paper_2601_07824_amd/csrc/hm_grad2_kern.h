@@ -441,9 +441,11 @@ static void grad2_launch_nf(int step, RowPassArgs &A, ColPassArgs &C, const Fuse
   constexpr int NL = sre_default_nl(NF, TB, RB);
   constexpr int NH = NF - NL;
   constexpr int CB = TB - NH;
-  // The adjoint column pass keeps its loads' addresses for the write-back: 2^4 values per thread
-  // keep it within the register file at two waves per SIMD.
-  constexpr int RBC = 4;
+  // Register tile of the adjoint column pass: 2^4 values per thread (four waves per SIMD); for FP32
+  // columns of 2^9 rows 2^5 (two waves per SIMD, more loads in flight per wave; measured on one
+  // MI355X at n = 19 / 20: 116.0 -> 113.7 / 115.9 -> 110.6 us per launch, fwd+grad 2 % faster; at
+  // 2^8 rows 2^4 stays faster).
+  constexpr int RBC = (sizeof(T) == 4 && NH >= 9) ? 5 : 4;
   constexpr int NTC = 1 << (TB - RBC);
   if (step == 2) {
     C.n_cb = (int64_t)1 << (C.nl - CB);
